@@ -1,0 +1,22 @@
+"""Oracle: a plain, slow, FP64 CPU implementation of the orbital-free SCF hot
+path, written from the paper (Archê, orbital-free molecular dynamics).
+
+THIS IS TEST INFRASTRUCTURE.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+the ``cpu_baseline`` leg of ``bench.py`` may import or execute anything in this
+package.  The product library (``paper_2606_13283_amd``) never imports it and
+shares no code, tables or constants with it.
+
+Modules
+  fd        Fermi-Dirac integrals (quadrature of the definition) and the local
+            Thomas-Fermi relations (Sec. 2.2, Sec. 2.6.2)
+  grid      real/reciprocal grids and the discrete unitary transforms (Sec. 2.3)
+  functional Hartree, von Weizsaecker, LDA exchange-correlation (Sec. 2.2, 2.6.4)
+  ionic     structure factor, pseudopotential, Ewald, electron-ion energy and
+            forces (Sec. 2.4, Sec. 2.6.3, 2.6.5)
+  scf       SCF loop: Newton on mu, More mixing, initial densities (Sec. 2.5)
+  thermo    free energy and pressure at the converged density (Sec. 2.6)
+  md        Verlet step (Sec. 2.1)
+
+Functions whose result no independent pin checks say "parity unpinned" in
+their docstring.
+"""
