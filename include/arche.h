@@ -1,0 +1,165 @@
+/*
+ * arche.h -- C ABI of the MI355X (gfx950) FP64 orbital-free SCF library
+ * (libarche.so).  The method is the one of "Arche, an orbital-free molecular
+ * dynamics code for fast production of equations of state": a finite-temperature
+ * Thomas-Fermi (+ lambda von Weizsaecker, + LDA exchange-correlation) electron
+ * density on a periodic grid, found by a self-consistent-field (SCF) iteration
+ * with a Newton search of the chemical potential and More's optimal mixing,
+ * followed by free energy, pressure and ionic forces, inside a Verlet MD loop.
+ *
+ * Conventions for every call:
+ *   - Hartree atomic units, FP64, C row-major arrays.
+ *   - Real grid fields are [Nx][Ny][Nz] (z fastest); grid point
+ *     (i,j,k) sits at (i Lx/Nx, j Ly/Ny, k Lz/Nz) (Sec. 2.3).
+ *   - Pointers named *_host are host memory owned by the caller; the library
+ *     copies in/out and keeps no reference after the call returns.
+ *   - The context owns all device memory it allocates (hipMalloc on the
+ *     device current at arche_scf_init) and frees it in arche_scf_free.
+ *   - Every call returns an arche_status; no call aborts or prints.  After an
+ *     error, arche_last_error(ctx) describes it.
+ *   - A context is used by one host thread at a time.
+ */
+#ifndef ARCHE_H
+#define ARCHE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct arche_ctx arche_ctx;
+
+typedef enum {
+  ARCHE_OK = 0,
+  ARCHE_EINVAL = -1,  /* invalid argument (sizes, NaN/inf positions, bad grid) */
+  ARCHE_ENOMEM = -2,  /* device or host allocation failed */
+  ARCHE_EHIP = -3,    /* a HIP runtime call failed */
+  ARCHE_ENOCONV = -4, /* SCF (or the mu search) did not converge; results hold the last iterate */
+  ARCHE_ESTATE = -5   /* call not valid in the current state (e.g. forces before a solve) */
+} arche_status;
+
+/* initial density of an SCF solve (Sec. 2.5, 2.5.1) */
+enum {
+  ARCHE_INIT_UNIFORM = 0,    /* n_0 = N_e / |Omega| */
+  ARCHE_INIT_ONE_CENTER = 1, /* superposition guess from the previous converged step; uniform if none */
+  ARCHE_INIT_KEEP = 2        /* the context's current density (e.g. from arche_set_density) */
+};
+/* density mixing (Sec. 2.5.2) */
+enum { ARCHE_MIX_FIXED = 0, ARCHE_MIX_MORE = 1 };
+/* exchange-correlation */
+enum { ARCHE_XC_NONE = 0, ARCHE_XC_LDA = 1 /* Dirac exchange + Perdew-Zunger 1981 correlation */ };
+
+typedef struct {
+  int32_t n_atoms;          /* N_i >= 1 */
+  int32_t n_species;        /* 1..8 */
+  const int32_t *species;   /* [n_atoms], values in [0, n_species) */
+  const double *Z;          /* [n_species] ionic charge Z_s > 0 */
+  const double *rc;         /* [n_species] empty-core radius r_c >= 0 (bohr): form factor
+                               V_s(k) = -Z_s cos(2 pi |k| r_c) / (pi |k|^2), k in 1/bohr (Sec. 2.4) */
+  const double *mass;       /* [n_species] ionic mass, electron masses (MD only) */
+  double cell[3];           /* orthorhombic cell edges L_x, L_y, L_z (bohr) */
+  int32_t grid[3];          /* N_x, N_y, N_z: even, factors 2, 3, 5 only, <= 1024 */
+  double kT;                /* electron temperature k_B T_e (Hartree) > 0 */
+  double lambda_vw;         /* von Weizsaecker coefficient lambda >= 0 */
+  int32_t xc;               /* ARCHE_XC_* */
+  double scf_tol;           /* stop when ||n_i - n_a||_2 / ||n_a||_2 < scf_tol */
+  int32_t scf_max_iter;     /* > 0 */
+  int32_t mixing;           /* ARCHE_MIX_* */
+  int32_t more_warmup;      /* More weight allowed from this iteration on (e.g. 3) */
+  double more_trust;        /* ... once max |n_i - n_a| / n_a <= more_trust (e.g. 0.5) */
+  double w_fixed;           /* fixed weight w of n_o = n_a + w (n_i - n_a) (e.g. 0.95) */
+  int32_t init;             /* ARCHE_INIT_* for arche_scf_solve */
+} arche_params;
+
+/* Energy terms (Hartree), index into arche_result.terms */
+enum {
+  ARCHE_T_FTF = 0,  /* int f0(n): Thomas-Fermi free energy */
+  ARCHE_T_KE,       /* K_e = (3/2) int p0: TF kinetic energy (Sec. 2.6.2) */
+  ARCHE_T_FVW,      /* von Weizsaecker energy */
+  ARCHE_T_EH,       /* Hartree energy U^ee (Sec. 2.6.4) */
+  ARCHE_T_FXC,      /* xc energy */
+  ARCHE_T_EIE,      /* electron-ion energy E^ie incl. the k=0 non-Coulomb term (Sec. 2.6.5) */
+  ARCHE_T_UII,      /* Ewald ion-ion energy U^ii (Sec. 2.6.3) */
+  ARCHE_T_UPP,
+  ARCHE_T_UPM,
+  ARCHE_T_UJE,
+  ARCHE_T_ALPHA,    /* Ewald splitting parameter used */
+  ARCHE_T_COUNT
+};
+/* Pressure terms (Hartree/bohr^3), index into arche_result.pterms */
+enum { ARCHE_P_TF = 0, ARCHE_P_VW, ARCHE_P_H, ARCHE_P_XC, ARCHE_P_IE, ARCHE_P_II, ARCHE_P_COUNT };
+
+typedef struct {
+  double F;                       /* free energy F = F_TF + F_vW + E_H + F_xc + E^ie + U^ii */
+  double E;                       /* internal energy (K_e in place of F_TF) */
+  double terms[ARCHE_T_COUNT];
+  double P;                       /* pressure without the ionic kinetic term */
+  double pterms[ARCHE_P_COUNT];
+  double mu;                      /* chemical potential */
+  double residual;                /* final ||n_i - n_a|| / ||n_a|| */
+  double w_last;                  /* last mixing weight */
+  int32_t scf_iters;
+  int32_t newton_iters;           /* total Newton passes of the mu search */
+  int32_t used_fallback;          /* one-center guess replaced by the uniform one */
+  int32_t converged;
+} arche_result;
+
+/* Create a context for one system (Sec. 2.3 grid, Sec. 2.4 pseudopotential).
+ * p: problem statement, copied (its arrays are copied too).
+ * hip_stream: hipStream_t to run on, or NULL for a stream the context creates.
+ * out: receives the context.  EINVAL on invalid parameters, ENOMEM/EHIP on
+ * device failures (no context is returned then). */
+arche_status arche_scf_init(const arche_params *p, void *hip_stream, arche_ctx **out);
+
+/* Solve the SCF (Sec. 2.5) for ions at pos_host [n_atoms][3] (bohr; wrapped
+ * into the cell), then evaluate free energy and pressure (Sec. 2.6) into *out.
+ * The initial density follows p.init.  ENOCONV if the SCF did not reach
+ * scf_tol within scf_max_iter (out still describes the last iterate), EINVAL
+ * for non-finite positions. */
+arche_status arche_scf_solve(arche_ctx *ctx, const double *pos_host, arche_result *out);
+
+/* Ionic forces F_j = F^ie + F^pm + F^pp (eq. force; Sec. 2.6.3, 2.6.5) at the
+ * last converged solve, into forces_host [n_atoms][3] (Hartree/bohr).
+ * ESTATE if there is no converged solve. */
+arche_status arche_forces(arche_ctx *ctx, double *forces_host);
+
+/* One Verlet step (Sec. 2.1).  On entry pos_io holds r(t) and vel_io v(t); if
+ * the context has no converged solve at r(t) one is made first.  The step sets
+ * r(t+dt) = 2 r(t) - r(t-dt) + F(t)/m dt^2 (with r(t-dt) = r(t) - v dt +
+ * F dt^2/(2m) on the first step), solves the SCF at r(t+dt) (initial density
+ * per p.init, normally one-center) and returns r(t+dt) in pos_io, the central
+ * difference v(t) = (r(t+dt) - r(t-dt)) / (2 dt) in vel_io, F(t+dt) in
+ * forces_out_host [n_atoms][3] (may be NULL) and the solve's result in *out.
+ * Positions are not wrapped on output. */
+arche_status arche_md_step(arche_ctx *ctx, double dt, double *pos_io, double *vel_io,
+                           double *forces_out_host, arche_result *out);
+
+/* Copy the converged density n_a [Nx][Ny][Nz] to dst (host if
+ * dst_on_device == 0, else device memory on the context's device).  ESTATE
+ * before a solve. */
+arche_status arche_get_density(arche_ctx *ctx, double *dst, int32_t dst_on_device);
+
+/* Replace the context's input density (used by the next solve with
+ * p.init == ARCHE_INIT_KEEP); src [Nx][Ny][Nz] host or device as above.  The
+ * density must be positive; it is rescaled to N_e electrons. */
+arche_status arche_set_density(arche_ctx *ctx, const double *src, int32_t src_on_device);
+
+/* Forget the previous step (next one-center guess falls back to uniform). */
+arche_status arche_reset_history(arche_ctx *ctx);
+
+void arche_scf_free(arche_ctx *ctx);
+
+/* Per-context message of the last error (empty if none); valid until the next
+ * call on ctx.  With ctx == NULL, the message of the last failed arche_scf_init
+ * in this thread. */
+const char *arche_last_error(const arche_ctx *ctx);
+
+const char *arche_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ARCHE_H */

@@ -1,0 +1,60 @@
+/*
+ * arche_kernels.h -- kernel-level entry points of libarche.so, for callers that
+ * hold their own device buffers (and for parity tests of single steps of the
+ * path).  Same conventions as arche.h: FP64, C row-major, arche_status returns,
+ * no call aborts or prints.  Pointers named d_* are device memory on the current
+ * HIP device, owned by the caller; `stream` is a hipStream_t (NULL = default).
+ * Complex arrays are interleaved (re, im) doubles.
+ */
+#ifndef ARCHE_KERNELS_H
+#define ARCHE_KERNELS_H
+
+#include "arche.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Unnormalised 3D real-to-complex DFT of the periodic grid of Sec. 2.3:
+ * d_out[i][j][k] = sum_r d_in[r] exp(-2 pi i (i x/Nx + j y/Ny + k z/Nz)) for
+ * k = 0..Nz/2 (half spectrum [Nx][Ny][Nz/2+1] complex).  grid as in
+ * arche_params.grid (EINVAL otherwise).  Blocks until done. */
+arche_status arche_k_fft_r2c(const int32_t grid[3], const double *d_in, double *d_out, void *stream);
+
+/* Inverse of the above without the 1/N factor: d_out[r] = sum over the full box of
+ * F(m) exp(+2 pi i m.r/N), with F the Hermitian extension of the half spectrum
+ * d_in (the imaginary parts of the self-conjugate k_z = 0 and N_z/2 entries do
+ * not enter, as for any real field).  d_in is not modified.  Blocks until done. */
+arche_status arche_k_fft_c2r(const int32_t grid[3], const double *d_in, double *d_out, void *stream);
+
+/* Complete Fermi-Dirac integrals I_j(x) = int_0^inf t^j/(exp(t-x)+1) dt
+ * (Sec. 2.2, with eq. SCF1) for j = -1/2, 1/2, 3/2 at n points d_x; any output
+ * may be NULL.  Blocks until done. */
+arche_status arche_k_fermi_dirac(int64_t n, const double *d_x, double *d_im12, double *d_ip12, double *d_ip32,
+                                 void *stream);
+
+/* Copies of internal fields of a context after a solve (host destination). */
+enum {
+  ARCHE_DBG_VIE = 0,    /* V^ie(r) [ng] (Sec. 2.4) */
+  ARCHE_DBG_VI = 1,     /* last input potential V_i [ng] */
+  ARCHE_DBG_NA = 2,     /* active density n_a [ng] */
+  ARCHE_DBG_NI = 3,     /* input density n_i [ng] */
+  ARCHE_DBG_SZP = 4,    /* charge structure factor S_Z(k) on the half box [nh] complex */
+  ARCHE_DBG_SZM = 5,    /* S_Z at k with its Nyquist components negated [nh] complex */
+  ARCHE_DBG_NHAT_A = 6, /* spectrum of n_a, (|Omega|/N_g) DFT, half box [nh] complex */
+  ARCHE_DBG_FPP = 7     /* real-space Ewald forces [n_atoms][3] */
+};
+arche_status arche_debug_get(arche_ctx *ctx, int32_t which, double *dst_host);
+
+/* One-center initial density (Sec. 2.5.1) for ions at pos_host from the last
+ * converged step, into n_init_host [ng]; *used_fallback = 1 if it fell back to the
+ * uniform density.  ESTATE without a converged previous step.  The context's next
+ * solve starts afresh (the guess is not kept as a solved state). */
+arche_status arche_debug_one_center(arche_ctx *ctx, const double *pos_host, double *n_init_host,
+                                    int32_t *used_fallback);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ARCHE_KERNELS_H */

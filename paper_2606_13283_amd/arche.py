@@ -1,0 +1,296 @@
+"""ctypes binding of libarche.so (C ABI in include/arche.h and
+include/arche_kernels.h).  Argument marshalling only: every step of the SCF
+path runs in the library's HIP kernels.  Device buffers for the kernel-level
+calls come from PyTorch (``tensor.data_ptr()``), which is used here for device
+memory and streams only.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libarche.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENOCONV, ESTATE = 0, -1, -2, -3, -4, -5
+INIT_UNIFORM, INIT_ONE_CENTER, INIT_KEEP = 0, 1, 2
+MIX_FIXED, MIX_MORE = 0, 1
+XC_NONE, XC_LDA = 0, 1
+TERM_NAMES = ("F_TF", "K_e", "F_vW", "E_H", "F_xc", "E_ie", "U_ii", "U_pp", "U_pm", "U_je", "alpha")
+PTERM_NAMES = ("P_TF", "P_vW", "P_H", "P_xc", "P_ie", "P_ii")
+DBG = dict(Vie=0, Vi=1, n_a=2, n_i=3, SZ_plus=4, SZ_minus=5, nhat_a=6, F_pp=7)
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+
+
+class ArcheError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("arche status %d: %s" % (status, msg))
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("n_atoms", ctypes.c_int32), ("n_species", ctypes.c_int32),
+        ("species", _ip), ("Z", _dp), ("rc", _dp), ("mass", _dp),
+        ("cell", ctypes.c_double * 3), ("grid", ctypes.c_int32 * 3),
+        ("kT", ctypes.c_double), ("lambda_vw", ctypes.c_double), ("xc", ctypes.c_int32),
+        ("scf_tol", ctypes.c_double), ("scf_max_iter", ctypes.c_int32), ("mixing", ctypes.c_int32),
+        ("more_warmup", ctypes.c_int32), ("more_trust", ctypes.c_double), ("w_fixed", ctypes.c_double),
+        ("init", ctypes.c_int32),
+    ]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [
+        ("F", ctypes.c_double), ("E", ctypes.c_double), ("terms", ctypes.c_double * 11),
+        ("P", ctypes.c_double), ("pterms", ctypes.c_double * 6), ("mu", ctypes.c_double),
+        ("residual", ctypes.c_double), ("w_last", ctypes.c_double),
+        ("scf_iters", ctypes.c_int32), ("newton_iters", ctypes.c_int32),
+        ("used_fallback", ctypes.c_int32), ("converged", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return dict(F=self.F, E=self.E, terms=dict(zip(TERM_NAMES, list(self.terms))), P=self.P,
+                    P_terms=dict(zip(PTERM_NAMES, list(self.pterms))), mu=self.mu, residual=self.residual,
+                    w_last=self.w_last, scf_iters=self.scf_iters, newton_iters=self.newton_iters,
+                    used_fallback=bool(self.used_fallback), converged=bool(self.converged))
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libarche.so.  Raises if it has not been built: there is no fallback."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libarche.so not found at %s; run paper_2606_13283_amd.build.build()" % path)
+    L = ctypes.CDLL(path)
+    st = ctypes.c_int
+    vp = ctypes.c_void_p
+    L.arche_scf_init.argtypes = [ctypes.POINTER(Params), vp, ctypes.POINTER(vp)]
+    L.arche_scf_init.restype = st
+    L.arche_scf_solve.argtypes = [vp, _dp, ctypes.POINTER(Result)]
+    L.arche_scf_solve.restype = st
+    L.arche_forces.argtypes = [vp, _dp]
+    L.arche_forces.restype = st
+    L.arche_md_step.argtypes = [vp, ctypes.c_double, _dp, _dp, _dp, ctypes.POINTER(Result)]
+    L.arche_md_step.restype = st
+    L.arche_get_density.argtypes = [vp, _dp, ctypes.c_int32]
+    L.arche_get_density.restype = st
+    L.arche_set_density.argtypes = [vp, _dp, ctypes.c_int32]
+    L.arche_set_density.restype = st
+    L.arche_reset_history.argtypes = [vp]
+    L.arche_reset_history.restype = st
+    L.arche_scf_free.argtypes = [vp]
+    L.arche_scf_free.restype = None
+    L.arche_last_error.argtypes = [vp]
+    L.arche_last_error.restype = ctypes.c_char_p
+    L.arche_version.argtypes = []
+    L.arche_version.restype = ctypes.c_char_p
+    L.arche_debug_get.argtypes = [vp, ctypes.c_int32, _dp]
+    L.arche_debug_get.restype = st
+    L.arche_debug_one_center.argtypes = [vp, _dp, _dp, _ip]
+    L.arche_debug_one_center.restype = st
+    L.arche_k_fft_r2c.argtypes = [_ip, vp, vp, vp]
+    L.arche_k_fft_r2c.restype = st
+    L.arche_k_fft_c2r.argtypes = [_ip, vp, vp, vp]
+    L.arche_k_fft_c2r.restype = st
+    L.arche_k_fermi_dirac.argtypes = [ctypes.c_int64, vp, vp, vp, vp, vp]
+    L.arche_k_fermi_dirac.restype = st
+    _lib = L
+    return L
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_dp)
+
+
+@dataclass
+class Options:
+    scf_tol: float = 1e-10
+    scf_max_iter: int = 5000
+    mixing: int = MIX_MORE
+    more_warmup: int = 3
+    more_trust: float = 0.5
+    w_fixed: float = 0.95
+    init: int = INIT_ONE_CENTER
+    lambda_vw: float = 0.2
+    xc: int = XC_LDA
+
+
+class Context:
+    """One system (cell, grid, species, temperature) on the current HIP device."""
+
+    def __init__(self, cell, grid, species, Z, rc, mass, kT, opts: Options | None = None, stream=None):
+        L = load()
+        o = opts or Options()
+        self._species = np.ascontiguousarray(np.asarray(species, dtype=np.int32).reshape(-1))
+        self._Z = _f64(Z).reshape(-1)
+        self._rc = _f64(rc).reshape(-1)
+        self._mass = _f64(mass).reshape(-1)
+        p = Params()
+        p.n_atoms = self._species.size
+        p.n_species = self._Z.size
+        p.species = self._species.ctypes.data_as(_ip)
+        p.Z, p.rc, p.mass = _ptr(self._Z), _ptr(self._rc), _ptr(self._mass)
+        for a in range(3):
+            p.cell[a] = float(cell[a])
+            p.grid[a] = int(grid[a])
+        p.kT = float(kT)
+        p.lambda_vw = float(o.lambda_vw)
+        p.xc = int(o.xc)
+        p.scf_tol = float(o.scf_tol)
+        p.scf_max_iter = int(o.scf_max_iter)
+        p.mixing = int(o.mixing)
+        p.more_warmup = int(o.more_warmup)
+        p.more_trust = float(o.more_trust)
+        p.w_fixed = float(o.w_fixed)
+        p.init = int(o.init)
+        self.params = p
+        self.n_atoms = p.n_atoms
+        self.grid = tuple(int(g) for g in grid)
+        self.nh = self.grid[0] * self.grid[1] * (self.grid[2] // 2 + 1)
+        h = ctypes.c_void_p()
+        s = L.arche_scf_init(ctypes.byref(p), ctypes.c_void_p(stream) if stream else None, ctypes.byref(h))
+        if s != OK:
+            raise ArcheError(s, L.arche_last_error(None).decode())
+        self._h = h
+        self._L = L
+
+    @classmethod
+    def from_workload(cls, w, opts: Options | None = None, stream=None):
+        return cls(w.cell, w.grid, w.species, w.Z, w.rc, w.mass, w.kT, opts, stream)
+
+    def _check(self, s, allow=()):
+        if s != OK and s not in allow:
+            raise ArcheError(s, self._L.arche_last_error(self._h).decode())
+        return s
+
+    def solve(self, pos, allow_noconv=False):
+        pos = _f64(pos, (self.n_atoms, 3))
+        r = Result()
+        s = self._L.arche_scf_solve(self._h, _ptr(pos), ctypes.byref(r))
+        self._check(s, (ENOCONV,) if allow_noconv else ())
+        return r.as_dict()
+
+    def forces(self):
+        F = np.empty((self.n_atoms, 3))
+        self._check(self._L.arche_forces(self._h, _ptr(F)))
+        return F
+
+    def md_step(self, dt, pos, vel):
+        pos = _f64(pos, (self.n_atoms, 3)).copy()
+        vel = _f64(vel, (self.n_atoms, 3)).copy()
+        F = np.empty((self.n_atoms, 3))
+        r = Result()
+        self._check(self._L.arche_md_step(self._h, float(dt), _ptr(pos), _ptr(vel), _ptr(F), ctypes.byref(r)))
+        return pos, vel, F, r.as_dict()
+
+    def density(self):
+        n = np.empty(self.grid)
+        self._check(self._L.arche_get_density(self._h, _ptr(n), 0))
+        return n
+
+    def set_density(self, n):
+        n = _f64(n, self.grid)
+        self._check(self._L.arche_set_density(self._h, _ptr(n), 0))
+
+    def reset_history(self):
+        self._check(self._L.arche_reset_history(self._h))
+
+    def debug(self, name):
+        w = DBG[name]
+        if name in ("SZ_plus", "SZ_minus", "nhat_a"):
+            out = np.empty(2 * self.nh)
+            self._check(self._L.arche_debug_get(self._h, w, _ptr(out)))
+            return out.view(np.complex128).reshape(self.grid[0], self.grid[1], self.grid[2] // 2 + 1)
+        if name == "F_pp":
+            out = np.empty((self.n_atoms, 3))
+        else:
+            out = np.empty(self.grid)
+        self._check(self._L.arche_debug_get(self._h, w, _ptr(out)))
+        return out
+
+    def one_center_guess(self, pos):
+        pos = _f64(pos, (self.n_atoms, 3))
+        out = np.empty(self.grid)
+        fb = ctypes.c_int32(0)
+        self._check(self._L.arche_debug_one_center(self._h, _ptr(pos), _ptr(out), ctypes.byref(fb)))
+        return out, bool(fb.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.arche_scf_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- kernel-level calls on torch device tensors ----
+
+def _grid_arr(grid):
+    return (ctypes.c_int32 * 3)(*[int(g) for g in grid])
+
+
+def fft_r2c(x):
+    """Unnormalised rfftn of a contiguous float64 cuda tensor [Nx, Ny, Nz] -> complex128 tensor."""
+    import torch
+    L = load()
+    x = x.contiguous()
+    Nx, Ny, Nz = x.shape
+    out = torch.empty((Nx, Ny, Nz // 2 + 1), dtype=torch.complex128, device=x.device)
+    s = L.arche_k_fft_r2c(_grid_arr(x.shape), ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                          ctypes.c_void_p(torch.cuda.current_stream(x.device).cuda_stream))
+    if s != OK:
+        raise ArcheError(s, "arche_k_fft_r2c")
+    return out
+
+
+def fft_c2r(X, Nz):
+    """Unnormalised inverse of fft_r2c (numpy irfftn times N) for a complex128 cuda tensor."""
+    import torch
+    L = load()
+    X = X.contiguous()
+    Nx, Ny, _ = X.shape
+    out = torch.empty((Nx, Ny, Nz), dtype=torch.float64, device=X.device)
+    s = L.arche_k_fft_c2r(_grid_arr((Nx, Ny, Nz)), ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                          ctypes.c_void_p(torch.cuda.current_stream(X.device).cuda_stream))
+    if s != OK:
+        raise ArcheError(s, "arche_k_fft_c2r")
+    return out
+
+
+def fermi_dirac(x):
+    """(I_{-1/2}, I_{1/2}, I_{3/2}) of a float64 cuda tensor."""
+    import torch
+    L = load()
+    x = x.contiguous()
+    a, b, c = (torch.empty_like(x) for _ in range(3))
+    s = L.arche_k_fermi_dirac(x.numel(), ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(a.data_ptr()),
+                              ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(c.data_ptr()),
+                              ctypes.c_void_p(torch.cuda.current_stream(x.device).cuda_stream))
+    if s != OK:
+        raise ArcheError(s, "arche_k_fermi_dirac")
+    return a, b, c
+
+
+def version():
+    return load().arche_version().decode()

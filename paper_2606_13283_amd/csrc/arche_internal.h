@@ -1,0 +1,127 @@
+// Internal state of one SCF context: device buffers, the device-resident SCF
+// scalars, and the kernel launchers shared by the translation units.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "../../include/arche.h"
+#include "common.h"
+#include "fft.h"
+
+// Scalars of the SCF iteration kept on the device (read back by the host only
+// to poll convergence).  Written by the kernels of scf.hip.
+struct ScfState {
+  double mu, N, dN;
+  double res;      // ||n_i - n_a|| / ||n_a||
+  double K;        // int dn^2 / (dn_a/dmu)
+  double Uxc;      // int (v_xc(n_i) - v_xc(n_a)) dn
+  double Uvw;      // int (v_vW[n_i] - v_vW[n_a]) dn
+  double UH;       // 1/|Omega| sum |dn^|^2 / (pi k^2)
+  double w;        // mixing weight of the last iteration
+  double maxrel;   // max |dn| / n_a
+  double Na;       // int n_a
+  int iter;        // completed SCF iterations
+  int newton_last;
+  int newton_total;
+  int done;
+  int more_on;
+  int mu_fail;
+  int err;         // barrier time-out or non-finite value
+  int pad;
+};
+
+struct GridInfo {
+  int N[3];
+  int Nh;
+  int64_t ng, nh;
+  double L[3];
+  double vol, dv;
+};
+
+// Per-species constants needed inside kernels.
+#define ARCHE_MAX_SPECIES 8
+struct SpeciesInfo {
+  int ns;
+  double Z[ARCHE_MAX_SPECIES];
+  double rc[ARCHE_MAX_SPECIES];
+};
+
+struct arche_ctx {
+  arche_params p;  // copy; pointer members are not kept
+  std::vector<int32_t> species;
+  std::vector<double> Z, rc, mass;
+  std::vector<double> Zj;  // per atom
+  int n_atoms = 0, n_species = 0;
+  double Ne = 0, Q = 0, sumZ2 = 0;
+  GridInfo g{};
+  SpeciesInfo sp{};
+  FftPlan plan{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int coop_blocks = 0;
+  std::string err;
+
+  // device fields (real: ng doubles, spectral: nh cplx)
+  double *Vie = nullptr, *VH = nullptr, *lap_i = nullptr, *n_i = nullptr, *n_a = nullptr, *Vi = nullptr,
+         *lap_a = nullptr, *rtmp = nullptr;
+  cplx *nhat_i = nullptr, *nhat_a = nullptr, *ctmp = nullptr, *ctmp2 = nullptr;
+  cplx *Sp = nullptr, *Sm = nullptr;  // per species [ns][nh]: S at box k and with Nyquist components negated
+  cplx *SZp = nullptr, *SZm = nullptr;
+  cplx *prev_nhat = nullptr, *prev_SZp = nullptr, *prev_SZm = nullptr;  // previous converged step
+  bool have_prev = false;
+  // one-center shells
+  int nshell = 0;
+  int32_t *shell_of = nullptr, *shell_perm = nullptr, *shell_off = nullptr;
+  double *shell_g = nullptr;
+  // atoms
+  double *pos = nullptr, *Zatom = nullptr, *forces = nullptr, *fpp = nullptr, *fpart = nullptr;
+  int32_t *spec_d = nullptr, *sp_order = nullptr, *sp_begin = nullptr;
+  cplx *Wp = nullptr, *Wm = nullptr;  // force weights per species [ns][nh]
+  cplx *phx = nullptr, *phy = nullptr, *phz = nullptr;  // [n_atoms][N] phase tables
+  // reductions
+  double *partials = nullptr;  // scratch for block partials
+  int partial_cap = 0;
+  double *sums = nullptr;      // small result vectors
+  ScfState *state = nullptr;
+  ScfState *state_host = nullptr;  // pinned mirror
+  unsigned *bar = nullptr;         // grid barrier count + generation
+  int *err_d = nullptr;
+  const FdTables *fdt = nullptr;
+
+  // host copies of the last solve
+  std::vector<double> h_pos, h_forces;
+  bool solved = false, converged = false, forces_ready = false;
+  double eta0 = 0;  // I_{1/2}^{-1}(n0/c_n)
+  arche_result last{};
+  // MD state
+  std::vector<double> r_prev;
+  bool have_r_prev = false;
+};
+
+// device Fermi-Dirac tables (uploaded once per process and device)
+const FdTables* fd_tables_device(int device);
+
+// kernels_*.hip launchers ---------------------------------------------------
+// reductions
+int red_blocks(int64_t n);
+hipError_t finish_sums(const double* partials, int nblk, int nsum, double* out, hipStream_t s);
+
+// SCF (scf.hip)
+hipError_t scf_iteration(arche_ctx* c);
+hipError_t scf_reset_state(arche_ctx* c, double mu0);
+hipError_t scf_vw_laplacian(arche_ctx* c, const double* n, double* lap);  // lap = del^2 sqrt(n)
+hipError_t scf_energies(arche_ctx* c, double* out16);  // see scf.hip for the order
+hipError_t scf_initial_uniform(arche_ctx* c);
+hipError_t scf_initial_one_center(arche_ctx* c, int* used_fallback);  // ionic.hip
+hipError_t scf_prepare_input(arche_ctx* c);  // n^_i, V_H, lap sqrt(n_i) from n_i
+int scf_coop_blocks(int64_t ng);
+
+// ionic (ionic.hip)
+hipError_t ionic_structure(arche_ctx* c);  // phases, S+/S-, SZ, V^ie
+hipError_t ionic_forces(arche_ctx* c, const cplx* nhat, double* forces_dev);
+hipError_t ionic_ewald(arche_ctx* c, double* U3 /*host: pp, pm, je*/, double alpha);
+hipError_t ionic_pressure_ie(arche_ctx* c, const cplx* nhat, double* out /*host*/);
+hipError_t ionic_shells(arche_ctx* c);
+size_t ionic_force_partials(const arche_ctx* c);
+double ewald_alpha(const arche_ctx* c);

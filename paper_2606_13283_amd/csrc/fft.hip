@@ -1,0 +1,378 @@
+// FP64 3D real<->complex FFT for gfx950 (see fft.h for the layout and passes).
+#include "fft.h"
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+namespace {
+
+struct Radices {
+  int nst;
+  int r[8];
+};
+
+// multiply by (sign * i)
+__device__ inline cplx mul_si(cplx z, double sign) { return cplx{-sign * z.y, sign * z.x}; }
+
+__device__ inline void bfly2(cplx* v) {
+  cplx a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+
+__device__ inline void bfly3(cplx* v, double sign) {
+  const double H = 0.86602540378443864676;  // sqrt(3)/2
+  cplx a = v[0], s = cadd(v[1], v[2]), d = csub(v[1], v[2]);
+  cplx m = cplx{a.x - 0.5 * s.x, a.y - 0.5 * s.y};
+  cplx t = mul_si(cscale(d, H), sign);
+  v[0] = cadd(a, s);
+  v[1] = cadd(m, t);
+  v[2] = csub(m, t);
+}
+
+__device__ inline void bfly4(cplx* v, double sign) {
+  cplx t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+  cplx t2 = cadd(v[1], v[3]), t3 = mul_si(csub(v[1], v[3]), sign);
+  v[0] = cadd(t0, t2);
+  v[2] = csub(t0, t2);
+  v[1] = cadd(t1, t3);
+  v[3] = csub(t1, t3);
+}
+
+__device__ inline void bfly5(cplx* v, double sign) {
+  const double C1 = 0.30901699437494742410;   // cos(2 pi/5)
+  const double C2 = -0.80901699437494742410;  // cos(4 pi/5)
+  const double S1 = 0.95105651629515357212;   // sin(2 pi/5)
+  const double S2 = 0.58778525229247312917;   // sin(4 pi/5)
+  cplx a = v[0];
+  cplx s1 = cadd(v[1], v[4]), d1 = csub(v[1], v[4]);
+  cplx s2 = cadd(v[2], v[3]), d2 = csub(v[2], v[3]);
+  cplx r1 = cplx{a.x + C1 * s1.x + C2 * s2.x, a.y + C1 * s1.y + C2 * s2.y};
+  cplx r2 = cplx{a.x + C2 * s1.x + C1 * s2.x, a.y + C2 * s1.y + C1 * s2.y};
+  cplx i1 = mul_si(cplx{S1 * d1.x + S2 * d2.x, S1 * d1.y + S2 * d2.y}, sign);
+  cplx i2 = mul_si(cplx{S2 * d1.x - S1 * d2.x, S2 * d1.y - S1 * d2.y}, sign);
+  v[0] = cadd(a, cadd(s1, s2));
+  v[1] = cadd(r1, i1);
+  v[4] = csub(r1, i1);
+  v[2] = cadd(r2, i2);
+  v[3] = csub(r2, i2);
+}
+
+template <int R>
+__device__ inline void bfly(cplx* v, double sg) {
+  if constexpr (R == 2) bfly2(v);
+  else if constexpr (R == 3) bfly3(v, sg);
+  else if constexpr (R == 4) bfly4(v, sg);
+  else bfly5(v, sg);
+}
+
+// One radix-R Stockham stage over `nlines` lines (all indices compile-time
+// unrolled in R, so the butterfly stays in registers).
+template <int R>
+__device__ inline void stockham_stage(const cplx* src, cplx* dst, const cplx* tw, int L, int nlines, int es,
+                                      int ls, int Ns, int sign, bool line_fast) {
+  const int nb = L / R;
+  const int total = nb * nlines;
+  const int tstep = L / (Ns * R);
+  const double sg = (double)sign;
+  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+    int line, j;
+    if (line_fast) {
+      line = t % nlines;
+      j = t / nlines;
+    } else {
+      j = t % nb;
+      line = t / nb;
+    }
+    const int k = j % Ns;
+    cplx v[R];
+    const cplx* in = src + line * ls;
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = in[(j + r * nb) * es];
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      cplx w = tw[r * k * tstep];
+      if (sign > 0) w.y = -w.y;
+      v[r] = cmul(v[r], w);
+    }
+    bfly<R>(v, sg);
+    const int base = (j / Ns) * Ns * R + k;
+    cplx* out = dst + line * ls;
+#pragma unroll
+    for (int r = 0; r < R; ++r) out[(base + r * Ns) * es] = v[r];
+  }
+}
+
+// Mixed-radix Stockham transform of `nlines` lines of length L held in LDS.
+// Element k of line b sits at buf[b*ls + k*es].  `line_fast` maps consecutive
+// threads to consecutive lines (for line-interleaved tiles) instead of to
+// consecutive butterflies of one line.  Returns the buffer holding the result.
+__device__ cplx* lds_fft(cplx* src, cplx* dst, const cplx* tw, int L, int nlines, int es, int ls,
+                         const Radices& rp, int sign, bool line_fast) {
+  int Ns = 1;
+  for (int s = 0; s < rp.nst; ++s) {
+    const int R = rp.r[s];
+    switch (R) {
+      case 2: stockham_stage<2>(src, dst, tw, L, nlines, es, ls, Ns, sign, line_fast); break;
+      case 3: stockham_stage<3>(src, dst, tw, L, nlines, es, ls, Ns, sign, line_fast); break;
+      case 4: stockham_stage<4>(src, dst, tw, L, nlines, es, ls, Ns, sign, line_fast); break;
+      default: stockham_stage<5>(src, dst, tw, L, nlines, es, ls, Ns, sign, line_fast); break;
+    }
+    __syncthreads();
+    cplx* tmp = src;
+    src = dst;
+    dst = tmp;
+    Ns *= R;
+  }
+  return src;
+}
+
+__global__ void __launch_bounds__(ARCHE_BLOCK)
+k_fft_z_r2c(const double* __restrict__ in, cplx* __restrict__ out, const cplx* __restrict__ tw_g,
+            int Nz, int Nh, int64_t npairs, int B, Radices rp, double in_scale, double out_scale) {
+  extern __shared__ cplx sm[];
+  const int pitch = Nz + 2;
+  cplx* a = sm;
+  cplx* b = sm + B * pitch;
+  cplx* tw = sm + 2 * B * pitch;
+  for (int i = threadIdx.x; i < Nz; i += blockDim.x) tw[i] = tw_g[i];
+  const int64_t p0 = (int64_t)blockIdx.x * B;
+  const int nb = (int)((npairs - p0) < B ? (npairs - p0) : B);
+  const double* src = in + p0 * 2 * Nz;
+  for (int q = threadIdx.x; q < nb * 2 * Nz; q += blockDim.x) {
+    int l = q / (2 * Nz);
+    int w = q - l * 2 * Nz;
+    int r = w / Nz;
+    int k = w - r * Nz;
+    double v = src[q] * in_scale;
+    if (r == 0)
+      a[l * pitch + k].x = v;
+    else
+      a[l * pitch + k].y = v;
+  }
+  __syncthreads();
+  cplx* res = lds_fft(a, b, tw, Nz, nb, 1, pitch, rp, -1, false);
+  cplx* dst = out + p0 * 2 * Nh;
+  for (int q = threadIdx.x; q < nb * 2 * Nh; q += blockDim.x) {
+    int l = q / (2 * Nh);
+    int w = q - l * 2 * Nh;
+    int r = w / Nh;
+    int k = w - r * Nh;
+    cplx zk = res[l * pitch + k];
+    cplx zn = res[l * pitch + (k == 0 ? 0 : Nz - k)];
+    cplx v;
+    if (r == 0)
+      v = cplx{0.5 * (zk.x + zn.x), 0.5 * (zk.y - zn.y)};
+    else
+      v = cplx{0.5 * (zk.y + zn.y), -0.5 * (zk.x - zn.x)};
+    dst[q] = cscale(v, out_scale);
+  }
+}
+
+__global__ void __launch_bounds__(ARCHE_BLOCK)
+k_fft_z_c2r(const cplx* __restrict__ in, double* __restrict__ out, const cplx* __restrict__ tw_g,
+            int Nz, int Nh, int64_t npairs, int B, Radices rp, double out_scale) {
+  extern __shared__ cplx sm[];
+  const int pitch = Nz + 2;
+  cplx* a = sm;
+  cplx* b = sm + B * pitch;
+  cplx* tw = sm + 2 * B * pitch;
+  for (int i = threadIdx.x; i < Nz; i += blockDim.x) tw[i] = tw_g[i];
+  const int64_t p0 = (int64_t)blockIdx.x * B;
+  const int nb = (int)((npairs - p0) < B ? (npairs - p0) : B);
+  const cplx* src = in + p0 * 2 * Nh;
+  // stage the two half rows of each pair (2*Nh <= pitch values) contiguously
+  for (int q = threadIdx.x; q < nb * 2 * Nh; q += blockDim.x) {
+    int l = q / (2 * Nh);
+    int w = q - l * 2 * Nh;
+    b[l * pitch + w] = src[q];
+  }
+  __syncthreads();
+  const int half = Nz / 2;
+  for (int q = threadIdx.x; q < nb * Nz; q += blockDim.x) {
+    int l = q / Nz;
+    int k = q - l * Nz;
+    const cplx* X = b + l * pitch;
+    const cplx* Y = X + Nh;
+    cplx x, y;
+    if (k == 0 || k == half) {
+      x = cplx{X[k].x, 0.0};
+      y = cplx{Y[k].x, 0.0};
+    } else if (k < half) {
+      x = X[k];
+      y = Y[k];
+    } else {
+      x = cconj(X[Nz - k]);
+      y = cconj(Y[Nz - k]);
+    }
+    a[l * pitch + k] = cplx{x.x - y.y, x.y + y.x};
+  }
+  __syncthreads();
+  cplx* res = lds_fft(a, b, tw, Nz, nb, 1, pitch, rp, +1, false);
+  double* dst = out + p0 * 2 * Nz;
+  for (int q = threadIdx.x; q < nb * 2 * Nz; q += blockDim.x) {
+    int l = q / (2 * Nz);
+    int w = q - l * 2 * Nz;
+    int r = w / Nz;
+    int k = w - r * Nz;
+    cplx z = res[l * pitch + k];
+    dst[q] = (r == 0 ? z.x : z.y) * out_scale;
+  }
+}
+
+__global__ void __launch_bounds__(ARCHE_BLOCK)
+k_fft_strided(cplx* __restrict__ data, const cplx* __restrict__ tw_g, int L, int64_t es, int64_t os,
+              int ncols, int TK, int nchunk, Radices rp, int sign, double scale) {
+  extern __shared__ cplx sm[];
+  cplx* a = sm;
+  cplx* b = sm + L * TK;
+  cplx* tw = sm + 2 * L * TK;
+  for (int i = threadIdx.x; i < L; i += blockDim.x) tw[i] = tw_g[i];
+  const int o = blockIdx.x / nchunk;
+  const int c0 = (blockIdx.x - o * nchunk) * TK;
+  const int nc = (ncols - c0) < TK ? (ncols - c0) : TK;
+  cplx* base = data + (int64_t)o * os + c0;
+  for (int q = threadIdx.x; q < L * TK; q += blockDim.x) {
+    int k = q / TK;
+    int c = q - k * TK;
+    a[q] = (c < nc) ? base[(int64_t)k * es + c] : cplx{0.0, 0.0};
+  }
+  __syncthreads();
+  cplx* res = lds_fft(a, b, tw, L, TK, TK, 1, rp, sign, true);
+  for (int q = threadIdx.x; q < L * TK; q += blockDim.x) {
+    int k = q / TK;
+    int c = q - k * TK;
+    if (c < nc) base[(int64_t)k * es + c] = cscale(res[q], scale);
+  }
+}
+
+Radices radices_of(const FftAxis& ax) {
+  Radices r;
+  r.nst = ax.nst;
+  for (int i = 0; i < 8; ++i) r.r[i] = ax.radix[i];
+  return r;
+}
+
+int z_rows_per_block(int Nz) {
+  int B = 1536 / (Nz + 2);
+  return B < 1 ? 1 : (B > 16 ? 16 : B);
+}
+
+int strided_tile(int L) { return L <= 64 ? 16 : 8; }
+
+hipError_t strided_pass(const FftPlan* p, cplx* data, int axis, int sign, double scale, hipStream_t s) {
+  const FftAxis& ax = p->ax[axis];
+  const int Nx = p->N[0], Ny = p->N[1], Nh = p->Nh;
+  int64_t es, os;
+  int nouter;
+  if (axis == 1) {  // lines along y: element stride Nh, one outer index per x
+    es = Nh;
+    os = (int64_t)Ny * Nh;
+    nouter = Nx;
+  } else {  // axis 0: lines along x, element stride Ny*Nh, one outer index per y
+    es = (int64_t)Ny * Nh;
+    os = Nh;
+    nouter = Ny;
+  }
+  const int TK = strided_tile(ax.L);
+  const int nchunk = (Nh + TK - 1) / TK;
+  const size_t lds = (size_t)(2 * ax.L * TK + ax.L) * sizeof(cplx);
+  hipLaunchKernelGGL(k_fft_strided, dim3(nouter * nchunk), dim3(ARCHE_BLOCK), lds, s, data, ax.tw, ax.L,
+                     es, os, Nh, TK, nchunk, radices_of(ax), sign, scale);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool fft_size_supported(int n) {
+  if (n < 2 || n > 1024 || (n & 1)) return false;
+  int r = n;
+  for (int p : {2, 3, 5})
+    while (r % p == 0) r /= p;
+  return r == 1;
+}
+
+static void factor(FftAxis& ax) {
+  int r = ax.L;
+  ax.nst = 0;
+  while (r % 4 == 0) {
+    ax.radix[ax.nst++] = 4;
+    r /= 4;
+  }
+  while (r % 2 == 0) {
+    ax.radix[ax.nst++] = 2;
+    r /= 2;
+  }
+  while (r % 3 == 0) {
+    ax.radix[ax.nst++] = 3;
+    r /= 3;
+  }
+  while (r % 5 == 0) {
+    ax.radix[ax.nst++] = 5;
+    r /= 5;
+  }
+  for (int i = ax.nst; i < 8; ++i) ax.radix[i] = 1;
+}
+
+bool fft_plan_create(FftPlan* plan, const int N[3]) {
+  std::memset(plan, 0, sizeof(*plan));
+  for (int a = 0; a < 3; ++a)
+    if (!fft_size_supported(N[a])) return false;
+  for (int a = 0; a < 3; ++a) {
+    plan->N[a] = N[a];
+    FftAxis& ax = plan->ax[a];
+    ax.L = N[a];
+    factor(ax);
+    if (ax.nst > 8) return false;
+    std::vector<cplx> tw(ax.L);
+    for (int m = 0; m < ax.L; ++m) {
+      long double ang = 2.0L * 3.141592653589793238462643383279502884L * (long double)m / (long double)ax.L;
+      tw[m] = cplx{(double)cosl(ang), (double)(-sinl(ang))};
+    }
+    if (hipMalloc(&ax.tw, ax.L * sizeof(cplx)) != hipSuccess) return false;
+    if (hipMemcpy(ax.tw, tw.data(), ax.L * sizeof(cplx), hipMemcpyHostToDevice) != hipSuccess) return false;
+  }
+  plan->Nh = N[2] / 2 + 1;
+  plan->ng = (int64_t)N[0] * N[1] * N[2];
+  plan->nh = (int64_t)N[0] * N[1] * plan->Nh;
+  plan->ok = true;
+  return true;
+}
+
+void fft_plan_destroy(FftPlan* plan) {
+  for (int a = 0; a < 3; ++a)
+    if (plan->ax[a].tw) (void)hipFree(plan->ax[a].tw);
+  std::memset(plan, 0, sizeof(*plan));
+}
+
+hipError_t fft_r2c(const FftPlan* p, const double* in, cplx* out, double in_scale, double out_scale,
+                   hipStream_t s) {
+  const FftAxis& az = p->ax[2];
+  const int Nz = p->N[2];
+  const int64_t npairs = (int64_t)p->N[0] * p->N[1] / 2;
+  const int B = z_rows_per_block(Nz);
+  const size_t lds = (size_t)(2 * B * (Nz + 2) + Nz) * sizeof(cplx);
+  hipLaunchKernelGGL(k_fft_z_r2c, dim3((unsigned)((npairs + B - 1) / B)), dim3(ARCHE_BLOCK), lds, s, in, out,
+                     az.tw, Nz, p->Nh, npairs, B, radices_of(az), in_scale, 1.0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = strided_pass(p, out, 1, -1, 1.0, s);
+  if (e != hipSuccess) return e;
+  return strided_pass(p, out, 0, -1, out_scale, s);
+}
+
+hipError_t fft_c2r(const FftPlan* p, cplx* in, double* out, double out_scale, hipStream_t s) {
+  hipError_t e = strided_pass(p, in, 0, +1, 1.0, s);
+  if (e != hipSuccess) return e;
+  e = strided_pass(p, in, 1, +1, 1.0, s);
+  if (e != hipSuccess) return e;
+  const FftAxis& az = p->ax[2];
+  const int Nz = p->N[2];
+  const int64_t npairs = (int64_t)p->N[0] * p->N[1] / 2;
+  const int B = z_rows_per_block(Nz);
+  const size_t lds = (size_t)(2 * B * (Nz + 2) + Nz) * sizeof(cplx);
+  hipLaunchKernelGGL(k_fft_z_c2r, dim3((unsigned)((npairs + B - 1) / B)), dim3(ARCHE_BLOCK), lds, s, in, out,
+                     az.tw, Nz, p->Nh, npairs, B, radices_of(az), out_scale);
+  return hipGetLastError();
+}

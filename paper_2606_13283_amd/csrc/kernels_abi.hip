@@ -1,0 +1,94 @@
+// Kernel-level entry points (include/arche_kernels.h): FFT and Fermi-Dirac
+// evaluation on caller-owned device buffers.
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "../../include/arche_kernels.h"
+#include "arche_internal.h"
+
+namespace {
+
+__global__ void __launch_bounds__(ARCHE_BLOCK)
+k_fd_eval(const FdTables* fdt, int64_t n, const double* x, double* im12, double* ip12, double* ip32) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = x[i];
+    double a, b;
+    fd_m12_p12(fdt, v, a, b);
+    if (im12) im12[i] = a;
+    if (ip12) ip12[i] = b;
+    if (ip32) ip32[i] = fd_eval_order(fdt, 2, v);
+  }
+}
+
+std::mutex g_plan_mtx;
+std::map<std::tuple<int, int, int, int>, FftPlan*> g_plans;  // (device, Nx, Ny, Nz), kept for the process
+
+FftPlan* plan_for(const int32_t grid[3]) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(g_plan_mtx);
+  auto key = std::make_tuple(dev, (int)grid[0], (int)grid[1], (int)grid[2]);
+  auto it = g_plans.find(key);
+  if (it != g_plans.end()) return it->second;
+  FftPlan* p = new FftPlan();
+  int N[3] = {grid[0], grid[1], grid[2]};
+  if (!fft_plan_create(p, N)) {
+    delete p;
+    return nullptr;
+  }
+  g_plans[key] = p;
+  return p;
+}
+
+bool grid_ok(const int32_t* grid) {
+  if (!grid) return false;
+  for (int a = 0; a < 3; ++a)
+    if (!fft_size_supported(grid[a])) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+arche_status arche_k_fft_r2c(const int32_t grid[3], const double* d_in, double* d_out, void* stream) {
+  if (!grid_ok(grid) || !d_in || !d_out) return ARCHE_EINVAL;
+  FftPlan* p = plan_for(grid);
+  if (!p) return ARCHE_ENOMEM;
+  hipStream_t s = (hipStream_t)stream;
+  if (fft_r2c(p, d_in, (cplx*)d_out, 1.0, 1.0, s) != hipSuccess) return ARCHE_EHIP;
+  return hipStreamSynchronize(s) == hipSuccess ? ARCHE_OK : ARCHE_EHIP;
+}
+
+arche_status arche_k_fft_c2r(const int32_t grid[3], const double* d_in, double* d_out, void* stream) {
+  if (!grid_ok(grid) || !d_in || !d_out) return ARCHE_EINVAL;
+  FftPlan* p = plan_for(grid);
+  if (!p) return ARCHE_ENOMEM;
+  hipStream_t s = (hipStream_t)stream;
+  cplx* work = nullptr;
+  if (hipMalloc(&work, p->nh * sizeof(cplx)) != hipSuccess) return ARCHE_ENOMEM;
+  hipError_t e = hipMemcpyAsync(work, d_in, p->nh * sizeof(cplx), hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = fft_c2r(p, work, d_out, 1.0, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(work);
+  return e == hipSuccess ? ARCHE_OK : ARCHE_EHIP;
+}
+
+arche_status arche_k_fermi_dirac(int64_t n, const double* d_x, double* d_im12, double* d_ip12, double* d_ip32,
+                                 void* stream) {
+  if (n < 0 || (n > 0 && !d_x)) return ARCHE_EINVAL;
+  if (n == 0) return ARCHE_OK;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return ARCHE_EHIP;
+  const FdTables* t = fd_tables_device(dev);
+  if (!t) return ARCHE_ENOMEM;
+  hipStream_t s = (hipStream_t)stream;
+  int64_t b = (n + ARCHE_BLOCK - 1) / ARCHE_BLOCK;
+  if (b > 4096) b = 4096;
+  hipLaunchKernelGGL(k_fd_eval, dim3((unsigned)b), dim3(ARCHE_BLOCK), 0, s, t, n, d_x, d_im12, d_ip12, d_ip32);
+  if (hipGetLastError() != hipSuccess) return ARCHE_EHIP;
+  return hipStreamSynchronize(s) == hipSuccess ? ARCHE_OK : ARCHE_EHIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,527 @@
+// Host runtime behind the C ABI: context lifecycle, SCF driver loop, energies,
+// pressure, forces and the Verlet MD step.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "../../include/arche_kernels.h"
+#include "arche_internal.h"
+
+namespace {
+
+constexpr double PI = 3.14159265358979323846;
+thread_local std::string g_init_err;
+
+// ---- host evaluation of I_{1/2} (same coefficient tables as the device) ----
+double fd_host(int j, double x) {
+  if (x < FD_X_LO) {
+    double y = std::exp(x), s = FD_SER[j][FD_KSER - 1];
+    for (int k = FD_KSER - 2; k >= 0; --k) s = std::fma(s, y, FD_SER[j][k]);
+    return y * s;
+  }
+  if (x >= FD_X_HI) {
+    double u = 1.0 / (x * x), s = FD_ASY[j][FD_KASY - 1];
+    for (int k = FD_KASY - 2; k >= 0; --k) s = std::fma(s, u, FD_ASY[j][k]);
+    double r = std::sqrt(x);
+    double p = (j == 0) ? 2.0 * r : (j == 1) ? x * r * (2.0 / 3.0) : x * x * r * 0.4;
+    return p * std::fma(u, s, 1.0);
+  }
+  int i = (int)std::floor(x - FD_X_LO);
+  i = std::max(0, std::min(FD_NINT - 1, i));
+  double t = 2.0 * (x - (FD_X_LO + i)) - 1.0;
+  double s = FD_POLY[j][i][FD_NCOEF - 1];
+  for (int k = FD_NCOEF - 2; k >= 0; --k) s = std::fma(s, t, FD_POLY[j][i][k]);
+  return s;
+}
+
+// X(y) = I_{1/2}^{-1}(y): Newton with a bisection safeguard on the monotone I_{1/2}
+double fd_inverse_p12(double y) {
+  double lo = std::log(y / 0.88622692545275801365) - 1e-9;  // I_{1/2}(x) < Gamma(3/2) e^x
+  double hi = std::max(std::pow(1.5 * y, 2.0 / 3.0), lo + 1.0) + 1.0;
+  while (fd_host(1, hi) < y) hi = 2.0 * hi + 1.0;
+  while (fd_host(1, lo) > y) lo -= 1.0;
+  double x = 0.5 * (lo + hi);
+  for (int it = 0; it < 200; ++it) {
+    double f = fd_host(1, x) - y;
+    if (f > 0) hi = x; else lo = x;
+    double xn = x - f / (0.5 * fd_host(0, x));
+    if (!(lo < xn && xn < hi)) xn = 0.5 * (lo + hi);
+    if (std::fabs(xn - x) <= 2e-16 * std::max(1.0, std::fabs(x))) return xn;
+    x = xn;
+  }
+  return x;
+}
+
+arche_status set_err(arche_ctx* c, arche_status s, const std::string& m) {
+  if (c) c->err = m;
+  return s;
+}
+
+arche_status hip_err(arche_ctx* c, hipError_t e, const char* what) {
+  return set_err(c, ARCHE_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define CK(x)                                              \
+  do {                                                     \
+    hipError_t e_ = (x);                                   \
+    if (e_ != hipSuccess) return hip_err(c, e_, #x);       \
+  } while (0)
+
+template <class T>
+hipError_t dalloc(T** p, size_t n) {
+  return hipMalloc((void**)p, std::max<size_t>(n, 1) * sizeof(T));
+}
+
+void free_all(arche_ctx* c) {
+  void* ptrs[] = {c->Vie, c->VH, c->lap_i, c->n_i, c->n_a, c->Vi, c->lap_a, c->rtmp, c->nhat_i, c->nhat_a, c->ctmp,
+                  c->ctmp2, c->Sp, c->Sm, c->SZp, c->SZm, c->prev_nhat, c->prev_SZp, c->prev_SZm, c->shell_of,
+                  c->shell_perm, c->shell_off, c->shell_g, c->pos, c->Zatom, c->forces, c->fpp, c->fpart, c->spec_d,
+                  c->sp_order, c->sp_begin, c->Wp, c->Wm, c->phx, c->phy, c->phz, c->partials, c->sums, c->state,
+                  c->bar, c->err_d};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (c->state_host) (void)hipHostFree(c->state_host);
+  if (c->plan.ok) fft_plan_destroy(&c->plan);
+}
+
+arche_status validate(const arche_params* p, std::string& msg) {
+  if (!p) return msg = "params is NULL", ARCHE_EINVAL;
+  if (p->n_atoms < 1) return msg = "n_atoms must be >= 1", ARCHE_EINVAL;
+  if (p->n_species < 1 || p->n_species > ARCHE_MAX_SPECIES) return msg = "n_species must be in 1..8", ARCHE_EINVAL;
+  if (!p->species || !p->Z || !p->rc || !p->mass) return msg = "species/Z/rc/mass arrays are required", ARCHE_EINVAL;
+  for (int j = 0; j < p->n_atoms; ++j)
+    if (p->species[j] < 0 || p->species[j] >= p->n_species) return msg = "species index out of range", ARCHE_EINVAL;
+  for (int s = 0; s < p->n_species; ++s) {
+    if (!(p->Z[s] > 0.0) || !std::isfinite(p->Z[s])) return msg = "Z must be positive", ARCHE_EINVAL;
+    if (!(p->rc[s] >= 0.0) || !std::isfinite(p->rc[s])) return msg = "rc must be >= 0", ARCHE_EINVAL;
+    if (!(p->mass[s] > 0.0) || !std::isfinite(p->mass[s])) return msg = "mass must be positive", ARCHE_EINVAL;
+  }
+  for (int a = 0; a < 3; ++a) {
+    if (!(p->cell[a] > 0.0) || !std::isfinite(p->cell[a])) return msg = "cell edges must be positive", ARCHE_EINVAL;
+    if (!fft_size_supported(p->grid[a]))
+      return msg = "grid sizes must be even, <= 1024, with prime factors 2, 3, 5 only", ARCHE_EINVAL;
+  }
+  if (!(p->kT > 0.0) || !std::isfinite(p->kT)) return msg = "kT must be positive", ARCHE_EINVAL;
+  if (!(p->lambda_vw >= 0.0) || !std::isfinite(p->lambda_vw)) return msg = "lambda_vw must be >= 0", ARCHE_EINVAL;
+  if (p->xc != ARCHE_XC_NONE && p->xc != ARCHE_XC_LDA) return msg = "unknown xc", ARCHE_EINVAL;
+  if (!(p->scf_tol > 0.0)) return msg = "scf_tol must be positive", ARCHE_EINVAL;
+  if (p->scf_max_iter < 1) return msg = "scf_max_iter must be >= 1", ARCHE_EINVAL;
+  if (p->mixing != ARCHE_MIX_FIXED && p->mixing != ARCHE_MIX_MORE) return msg = "unknown mixing", ARCHE_EINVAL;
+  if (!(p->w_fixed >= 0.0 && p->w_fixed < 1.0)) return msg = "w_fixed must be in [0, 1)", ARCHE_EINVAL;
+  if (p->more_warmup < 0) return msg = "more_warmup must be >= 0", ARCHE_EINVAL;
+  if (!(p->more_trust > 0.0)) return msg = "more_trust must be positive", ARCHE_EINVAL;
+  if (p->init < ARCHE_INIT_UNIFORM || p->init > ARCHE_INIT_KEEP) return msg = "unknown init", ARCHE_EINVAL;
+  return ARCHE_OK;
+}
+
+// SCF loop: one queued iteration ahead of the convergence poll
+arche_status run_scf(arche_ctx* c, arche_result* out) {
+  CK(scf_reset_state(c, NAN));
+  hipEvent_t ev[2];
+  CK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+  CK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+  ScfState* ring = c->state_host;  // [2] pinned
+  bool stop = false;
+  int t = 0;
+  for (; t < c->p.scf_max_iter && !stop; ++t) {
+    hipError_t e = scf_iteration(c);
+    if (e == hipSuccess) e = hipMemcpyAsync(&ring[t & 1], c->state, sizeof(ScfState), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(ev[t & 1], c->stream);
+    if (e == hipSuccess && t >= 1) {
+      e = hipEventSynchronize(ev[(t - 1) & 1]);
+      if (e == hipSuccess && ring[(t - 1) & 1].done) stop = true;
+    }
+    if (e != hipSuccess) {
+      (void)hipEventDestroy(ev[0]);
+      (void)hipEventDestroy(ev[1]);
+      return hip_err(c, e, "scf iteration");
+    }
+  }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  ScfState st;
+  CK(hipMemcpyAsync(&st, c->state, sizeof(ScfState), hipMemcpyDeviceToHost, c->stream));
+  CK(hipStreamSynchronize(c->stream));
+  std::memset(out, 0, sizeof(*out));
+  out->mu = st.mu;
+  out->residual = st.res;
+  out->w_last = st.w;
+  out->scf_iters = st.iter;
+  out->newton_iters = st.newton_total;
+  out->converged = st.done && !st.err && st.res < c->p.scf_tol;
+  c->converged = out->converged;
+  if (st.err) {
+    c->err = st.mu_fail ? "chemical-potential search did not converge" : "non-finite value or barrier time-out in SCF";
+  } else if (!out->converged) {
+    c->err = "SCF did not reach scf_tol within scf_max_iter";
+  }
+  return ARCHE_OK;
+}
+
+arche_status evaluate(arche_ctx* c, arche_result* out) {
+  double e[9];
+  CK(scf_energies(c, e));
+  const double alpha = ewald_alpha(c);
+  double U3[3];
+  CK(ionic_ewald(c, U3, alpha));
+  double pie = 0.0;
+  CK(ionic_pressure_ie(c, c->nhat_a, &pie));
+  const GridInfo& g = c->g;
+  double Ealpha = 0.0;
+  for (int j = 0; j < c->n_atoms; ++j) {
+    const int s = c->species[j];
+    Ealpha += 2.0 * PI * c->Z[s] * c->rc[s] * c->rc[s];
+  }
+  Ealpha *= c->Ne / g.vol;
+  const double Eie = e[4] + Ealpha;
+  const double Uii = U3[0] + U3[1] + U3[2];
+  out->terms[ARCHE_T_FTF] = e[0];
+  out->terms[ARCHE_T_KE] = e[1];
+  out->terms[ARCHE_T_FVW] = e[7];
+  out->terms[ARCHE_T_EH] = e[6];
+  out->terms[ARCHE_T_FXC] = e[2];
+  out->terms[ARCHE_T_EIE] = Eie;
+  out->terms[ARCHE_T_UII] = Uii;
+  out->terms[ARCHE_T_UPP] = U3[0];
+  out->terms[ARCHE_T_UPM] = U3[1];
+  out->terms[ARCHE_T_UJE] = U3[2];
+  out->terms[ARCHE_T_ALPHA] = alpha;
+  out->F = e[0] + e[7] + e[6] + e[2] + Eie + Uii;
+  out->E = e[1] + e[7] + e[6] + e[2] + Eie + Uii;
+  out->pterms[ARCHE_P_TF] = e[8];
+  out->pterms[ARCHE_P_VW] = 2.0 * e[7] / (3.0 * g.vol);
+  out->pterms[ARCHE_P_H] = e[6] / (3.0 * g.vol);
+  out->pterms[ARCHE_P_XC] = e[3];
+  out->pterms[ARCHE_P_IE] = Eie / g.vol + pie / (3.0 * g.vol * g.vol);
+  out->pterms[ARCHE_P_II] = Uii / (3.0 * g.vol);
+  out->P = 0.0;
+  for (int k = 0; k < ARCHE_P_COUNT; ++k) out->P += out->pterms[k];
+  return ARCHE_OK;
+}
+
+arche_status do_solve(arche_ctx* c, const double* pos_host, arche_result* out, int init) {
+  const int n = c->n_atoms;
+  for (int q = 0; q < 3 * n; ++q)
+    if (!std::isfinite(pos_host[q])) return set_err(c, ARCHE_EINVAL, "non-finite position");
+  c->err.clear();
+  c->h_pos.assign(pos_host, pos_host + 3 * n);
+  c->forces_ready = false;
+  CK(hipMemcpyAsync(c->pos, c->h_pos.data(), 3 * n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  CK(ionic_structure(c));
+  int fallback = 0;
+  if (init == ARCHE_INIT_ONE_CENTER && c->have_prev) {
+    CK(scf_initial_one_center(c, &fallback));
+  } else if (init == ARCHE_INIT_KEEP && c->solved) {
+    CK(scf_prepare_input(c));
+  } else {
+    CK(scf_initial_uniform(c));
+  }
+  arche_status s = run_scf(c, out);
+  if (s != ARCHE_OK) return s;
+  out->used_fallback = fallback;
+  s = evaluate(c, out);
+  if (s != ARCHE_OK) return s;
+  // keep the converged spectrum and the charge structure factor for the next one-center guess
+  const size_t hb = c->g.nh * sizeof(cplx);
+  CK(hipMemcpyAsync(c->prev_nhat, c->nhat_a, hb, hipMemcpyDeviceToDevice, c->stream));
+  CK(hipMemcpyAsync(c->prev_SZp, c->SZp, hb, hipMemcpyDeviceToDevice, c->stream));
+  CK(hipMemcpyAsync(c->prev_SZm, c->SZm, hb, hipMemcpyDeviceToDevice, c->stream));
+  CK(hipStreamSynchronize(c->stream));
+  c->have_prev = out->converged;
+  c->solved = true;
+  c->last = *out;
+  return out->converged ? ARCHE_OK : ARCHE_ENOCONV;
+}
+
+arche_status do_forces(arche_ctx* c) {
+  if (!c->forces_ready) {
+    CK(ionic_forces(c, c->nhat_a, c->forces));
+    c->h_forces.resize(3 * c->n_atoms);
+    CK(hipMemcpyAsync(c->h_forces.data(), c->forces, 3 * c->n_atoms * sizeof(double), hipMemcpyDeviceToHost,
+                      c->stream));
+    CK(hipStreamSynchronize(c->stream));
+    c->forces_ready = true;
+  }
+  return ARCHE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+arche_status arche_scf_init(const arche_params* p, void* hip_stream, arche_ctx** out) {
+  if (!out) {
+    g_init_err = "out is NULL";
+    return ARCHE_EINVAL;
+  }
+  *out = nullptr;
+  std::string msg;
+  arche_status vs = validate(p, msg);
+  if (vs != ARCHE_OK) {
+    g_init_err = msg;
+    return vs;
+  }
+  arche_ctx* c = new (std::nothrow) arche_ctx();
+  if (!c) {
+    g_init_err = "host allocation failed";
+    return ARCHE_ENOMEM;
+  }
+  c->p = *p;
+  c->p.species = nullptr;
+  c->p.Z = c->p.rc = c->p.mass = nullptr;
+  c->n_atoms = p->n_atoms;
+  c->n_species = p->n_species;
+  c->species.assign(p->species, p->species + p->n_atoms);
+  c->Z.assign(p->Z, p->Z + p->n_species);
+  c->rc.assign(p->rc, p->rc + p->n_species);
+  c->mass.assign(p->mass, p->mass + p->n_species);
+  c->Zj.resize(c->n_atoms);
+  for (int j = 0; j < c->n_atoms; ++j) {
+    c->Zj[j] = c->Z[c->species[j]];
+    c->Ne += c->Zj[j];
+    c->sumZ2 += c->Zj[j] * c->Zj[j];
+  }
+  c->Q = c->Ne;
+  GridInfo& g = c->g;
+  for (int a = 0; a < 3; ++a) {
+    g.N[a] = p->grid[a];
+    g.L[a] = p->cell[a];
+  }
+  g.Nh = g.N[2] / 2 + 1;
+  g.ng = (int64_t)g.N[0] * g.N[1] * g.N[2];
+  g.nh = (int64_t)g.N[0] * g.N[1] * g.Nh;
+  g.vol = g.L[0] * g.L[1] * g.L[2];
+  g.dv = g.vol / (double)g.ng;
+  c->sp.ns = c->n_species;
+  for (int s = 0; s < c->n_species; ++s) {
+    c->sp.Z[s] = c->Z[s];
+    c->sp.rc[s] = c->rc[s];
+  }
+  const double cn = std::pow(2.0 * p->kT, 1.5) / (2.0 * PI * PI);
+  c->eta0 = fd_inverse_p12(c->Ne / g.vol / cn);
+
+  auto fail_init = [&](arche_status s, const std::string& m) {
+    g_init_err = m;
+    free_all(c);
+    if (c->stream && !hip_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return s;
+  };
+  if (hipGetDevice(&c->device) != hipSuccess) return fail_init(ARCHE_EHIP, "no HIP device");
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+  } else if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+    return fail_init(ARCHE_EHIP, "hipStreamCreate failed");
+  }
+  int dev_attr = 0;
+  (void)hipDeviceGetAttribute(&dev_attr, hipDeviceAttributeCooperativeLaunch, c->device);
+  if (!dev_attr) return fail_init(ARCHE_EHIP, "device does not support cooperative launches");
+  if (!fft_plan_create(&c->plan, g.N)) return fail_init(ARCHE_ENOMEM, "FFT plan creation failed");
+  c->fdt = fd_tables_device(c->device);
+  if (!c->fdt) return fail_init(ARCHE_ENOMEM, "Fermi-Dirac table upload failed");
+  c->coop_blocks = scf_coop_blocks(g.ng);
+  if (c->coop_blocks < 1) return fail_init(ARCHE_EHIP, "cooperative occupancy query failed");
+
+  const int ns = c->n_species, n = c->n_atoms;
+  bool ok = true;
+  for (double** f : {&c->Vie, &c->VH, &c->lap_i, &c->n_i, &c->n_a, &c->Vi, &c->lap_a, &c->rtmp})
+    ok = ok && dalloc(f, g.ng) == hipSuccess;
+  for (cplx** f : {&c->nhat_i, &c->nhat_a, &c->ctmp, &c->ctmp2, &c->SZp, &c->SZm, &c->prev_nhat, &c->prev_SZp,
+                   &c->prev_SZm})
+    ok = ok && dalloc(f, g.nh) == hipSuccess;
+  for (cplx** f : {&c->Sp, &c->Sm, &c->Wp, &c->Wm}) ok = ok && dalloc(f, (size_t)ns * g.nh) == hipSuccess;
+  ok = ok && dalloc(&c->phx, (size_t)n * g.N[0]) == hipSuccess;
+  ok = ok && dalloc(&c->phy, (size_t)n * g.N[1]) == hipSuccess;
+  ok = ok && dalloc(&c->phz, (size_t)n * g.Nh) == hipSuccess;
+  ok = ok && dalloc(&c->pos, 3 * (size_t)n) == hipSuccess;
+  ok = ok && dalloc(&c->Zatom, (size_t)n) == hipSuccess;
+  ok = ok && dalloc(&c->forces, 3 * (size_t)n) == hipSuccess;
+  ok = ok && dalloc(&c->fpp, 3 * (size_t)n) == hipSuccess;
+  ok = ok && dalloc(&c->spec_d, (size_t)n) == hipSuccess;
+  ok = ok && dalloc(&c->sp_order, (size_t)n) == hipSuccess;
+  ok = ok && dalloc(&c->sp_begin, (size_t)ns + 1) == hipSuccess;
+  c->partial_cap = 16 * c->coop_blocks + 8 * 1024 + n + 64;
+  ok = ok && dalloc(&c->partials, (size_t)c->partial_cap) == hipSuccess;
+  ok = ok && dalloc(&c->sums, 64) == hipSuccess;
+  ok = ok && dalloc(&c->state, 1) == hipSuccess;
+  ok = ok && dalloc(&c->bar, 2) == hipSuccess;
+  ok = ok && dalloc(&c->err_d, 1) == hipSuccess;
+  if (ok) ok = dalloc(&c->fpart, ionic_force_partials(c)) == hipSuccess;
+  if (ok) ok = hipHostMalloc((void**)&c->state_host, 2 * sizeof(ScfState), hipHostMallocDefault) == hipSuccess;
+  if (!ok) return fail_init(ARCHE_ENOMEM, "device allocation failed");
+  std::vector<int32_t> order(n), begin(ns + 1, 0);
+  {
+    int q = 0;
+    for (int s = 0; s < ns; ++s) {
+      begin[s] = q;
+      for (int j = 0; j < n; ++j)
+        if (c->species[j] == s) order[q++] = j;
+    }
+    begin[ns] = q;
+  }
+  bool up = hipMemcpy(c->Zatom, c->Zj.data(), n * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(c->spec_d, c->species.data(), n * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(c->sp_order, order.data(), n * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(c->sp_begin, begin.data(), (ns + 1) * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess;
+  if (!up) return fail_init(ARCHE_EHIP, "upload failed");
+  if (ionic_shells(c) != hipSuccess) return fail_init(ARCHE_ENOMEM, "shell table allocation failed");
+  *out = c;
+  return ARCHE_OK;
+}
+
+arche_status arche_scf_solve(arche_ctx* c, const double* pos_host, arche_result* out) {
+  if (!c || !pos_host || !out) return set_err(c, ARCHE_EINVAL, "NULL argument");
+  return do_solve(c, pos_host, out, c->p.init);
+}
+
+arche_status arche_forces(arche_ctx* c, double* forces_host) {
+  if (!c || !forces_host) return set_err(c, ARCHE_EINVAL, "NULL argument");
+  if (!c->solved || !c->converged) return set_err(c, ARCHE_ESTATE, "no converged solve");
+  arche_status s = do_forces(c);
+  if (s != ARCHE_OK) return s;
+  std::memcpy(forces_host, c->h_forces.data(), 3 * c->n_atoms * sizeof(double));
+  return ARCHE_OK;
+}
+
+arche_status arche_md_step(arche_ctx* c, double dt, double* pos_io, double* vel_io, double* forces_out,
+                           arche_result* out) {
+  if (!c || !pos_io || !vel_io || !out) return set_err(c, ARCHE_EINVAL, "NULL argument");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return set_err(c, ARCHE_EINVAL, "dt must be positive");
+  const int n = c->n_atoms;
+  for (int q = 0; q < 3 * n; ++q)
+    if (!std::isfinite(pos_io[q]) || !std::isfinite(vel_io[q])) return set_err(c, ARCHE_EINVAL, "non-finite input");
+  const bool same = c->solved && c->converged && c->h_pos.size() == (size_t)3 * n &&
+                    std::memcmp(c->h_pos.data(), pos_io, 3 * n * sizeof(double)) == 0;
+  if (!same) {
+    c->have_r_prev = false;
+    arche_result tmp;
+    arche_status s = do_solve(c, pos_io, &tmp, c->p.init);
+    if (s != ARCHE_OK) return s;
+  }
+  arche_status s = do_forces(c);
+  if (s != ARCHE_OK) return s;
+  std::vector<double> r(pos_io, pos_io + 3 * n), F = c->h_forces, rn(3 * n), v(3 * n);
+  if (!c->have_r_prev) {
+    c->r_prev.resize(3 * n);
+    for (int j = 0; j < n; ++j) {
+      const double m = c->mass[c->species[j]];
+      for (int a = 0; a < 3; ++a)
+        c->r_prev[3 * j + a] = r[3 * j + a] - vel_io[3 * j + a] * dt + F[3 * j + a] * dt * dt / (2.0 * m);
+    }
+  }
+  for (int j = 0; j < n; ++j) {
+    const double m = c->mass[c->species[j]];
+    for (int a = 0; a < 3; ++a) {
+      const int q = 3 * j + a;
+      rn[q] = 2.0 * r[q] - c->r_prev[q] + F[q] * dt * dt / m;
+      v[q] = (rn[q] - c->r_prev[q]) / (2.0 * dt);
+    }
+  }
+  s = do_solve(c, rn.data(), out, c->p.init);
+  if (s != ARCHE_OK) {
+    c->have_r_prev = false;
+    return s;
+  }
+  c->r_prev = r;
+  c->have_r_prev = true;
+  s = do_forces(c);
+  if (s != ARCHE_OK) return s;
+  std::memcpy(pos_io, rn.data(), 3 * n * sizeof(double));
+  std::memcpy(vel_io, v.data(), 3 * n * sizeof(double));
+  if (forces_out) std::memcpy(forces_out, c->h_forces.data(), 3 * n * sizeof(double));
+  return ARCHE_OK;
+}
+
+arche_status arche_get_density(arche_ctx* c, double* dst, int32_t on_device) {
+  if (!c || !dst) return set_err(c, ARCHE_EINVAL, "NULL argument");
+  if (!c->solved) return set_err(c, ARCHE_ESTATE, "no solve yet");
+  CK(hipMemcpyAsync(dst, c->n_a, c->g.ng * sizeof(double), on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                    c->stream));
+  CK(hipStreamSynchronize(c->stream));
+  return ARCHE_OK;
+}
+
+arche_status arche_set_density(arche_ctx* c, const double* src, int32_t on_device) {
+  if (!c || !src) return set_err(c, ARCHE_EINVAL, "NULL argument");
+  const GridInfo& g = c->g;
+  std::vector<double> h;
+  if (on_device) {
+    h.resize(g.ng);
+    CK(hipMemcpy(h.data(), src, g.ng * sizeof(double), hipMemcpyDeviceToHost));
+    src = h.data();
+  }
+  double tot = 0.0;
+  for (int64_t i = 0; i < g.ng; ++i) {
+    if (!(src[i] > 0.0) || !std::isfinite(src[i])) return set_err(c, ARCHE_EINVAL, "density must be positive");
+    tot += src[i];
+  }
+  const double s = c->Ne / (tot * g.dv);
+  std::vector<double> n(src, src + g.ng);
+  for (auto& v : n) v *= s;
+  CK(hipMemcpyAsync(c->n_i, n.data(), g.ng * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  CK(hipStreamSynchronize(c->stream));
+  c->solved = true;  // an input density exists for ARCHE_INIT_KEEP
+  c->converged = false;
+  return ARCHE_OK;
+}
+
+arche_status arche_reset_history(arche_ctx* c) {
+  if (!c) return ARCHE_EINVAL;
+  c->have_prev = false;
+  c->have_r_prev = false;
+  return ARCHE_OK;
+}
+
+void arche_scf_free(arche_ctx* c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  free_all(c);
+  delete c;
+}
+
+const char* arche_last_error(const arche_ctx* c) { return c ? c->err.c_str() : g_init_err.c_str(); }
+
+const char* arche_version(void) { return "arche-mi355x 0.1 (gfx950, FP64)"; }
+
+arche_status arche_debug_get(arche_ctx* c, int32_t which, double* dst_host) {
+  if (!c || !dst_host) return set_err(c, ARCHE_EINVAL, "NULL argument");
+  const GridInfo& g = c->g;
+  const void* src = nullptr;
+  size_t bytes = 0;
+  switch (which) {
+    case ARCHE_DBG_VIE: src = c->Vie; bytes = g.ng * sizeof(double); break;
+    case ARCHE_DBG_VI: src = c->Vi; bytes = g.ng * sizeof(double); break;
+    case ARCHE_DBG_NA: src = c->n_a; bytes = g.ng * sizeof(double); break;
+    case ARCHE_DBG_NI: src = c->n_i; bytes = g.ng * sizeof(double); break;
+    case ARCHE_DBG_SZP: src = c->SZp; bytes = g.nh * sizeof(cplx); break;
+    case ARCHE_DBG_SZM: src = c->SZm; bytes = g.nh * sizeof(cplx); break;
+    case ARCHE_DBG_NHAT_A: src = c->nhat_a; bytes = g.nh * sizeof(cplx); break;
+    case ARCHE_DBG_FPP: src = c->fpp; bytes = 3 * c->n_atoms * sizeof(double); break;
+    default: return set_err(c, ARCHE_EINVAL, "unknown debug field");
+  }
+  CK(hipMemcpyAsync(dst_host, src, bytes, hipMemcpyDeviceToHost, c->stream));
+  CK(hipStreamSynchronize(c->stream));
+  return ARCHE_OK;
+}
+
+arche_status arche_debug_one_center(arche_ctx* c, const double* pos_host, double* n_init_host, int32_t* used_fallback) {
+  if (!c || !pos_host || !n_init_host) return set_err(c, ARCHE_EINVAL, "NULL argument");
+  if (!c->have_prev) return set_err(c, ARCHE_ESTATE, "no previous converged step");
+  c->h_pos.assign(pos_host, pos_host + 3 * c->n_atoms);
+  CK(hipMemcpyAsync(c->pos, pos_host, 3 * c->n_atoms * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  CK(ionic_structure(c));
+  int fb = 0;
+  CK(scf_initial_one_center(c, &fb));
+  if (used_fallback) *used_fallback = fb;
+  CK(hipMemcpyAsync(n_init_host, c->n_i, c->g.ng * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  CK(hipStreamSynchronize(c->stream));
+  c->solved = false;
+  c->converged = false;
+  return ARCHE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,648 @@
+// SCF iteration kernels (paper Sec. 2.5): potential assembly, Newton search of
+// mu, active density, More mixing weight, mixed density, Hartree and von
+// Weizsaecker potentials; and the energy reductions of Sec. 2.6.
+#include <algorithm>
+#include <cmath>
+#include <mutex>
+
+#include "arche_internal.h"
+
+namespace {
+
+constexpr double PI = 3.14159265358979323846;
+
+// ---------------------------------------------------------------------------
+// partial-sum helpers
+__device__ inline double reduce_slot_sum(const double* part, int slot, unsigned nb, double* sh) {
+  double v = 0.0;
+  const double* p = part + (size_t)slot * nb;
+  for (unsigned t = threadIdx.x; t < nb; t += blockDim.x) v += coherent_load(p + t);
+  v = block_sum(v, sh);
+  __shared__ double bc;
+  if (threadIdx.x == 0) bc = v;
+  __syncthreads();
+  double r = bc;
+  __syncthreads();
+  return r;
+}
+
+__device__ inline double reduce_slot_max(const double* part, int slot, unsigned nb, double* sh) {
+  double v = -INFINITY;
+  const double* p = part + (size_t)slot * nb;
+  for (unsigned t = threadIdx.x; t < nb; t += blockDim.x) v = fmax(v, coherent_load(p + t));
+  v = block_max(v, sh);
+  __shared__ double bc;
+  if (threadIdx.x == 0) bc = v;
+  __syncthreads();
+  double r = bc;
+  __syncthreads();
+  return r;
+}
+
+__device__ inline void put_slot(double* part, int slot, unsigned nb, double v) {
+  if (threadIdx.x == 0) coherent_store(part + (size_t)slot * nb + blockIdx.x, v);
+}
+
+struct ActiveArgs {
+  const double* Vie;
+  const double* VH;
+  const double* lap_i;
+  const double* n_i;
+  double* Vi;
+  double* n_a;
+  ScfState* st;
+  double* part;
+  unsigned* bar;
+  int* err;
+  const FdTables* fdt;
+  int64_t ng;
+  double dv, kT, cn, Ne, lam;
+  int xc;
+  double eta0, tol;
+  int mixing, warmup;
+  double trust;
+  int max_newton;
+};
+
+// One cooperative launch per SCF iteration: steps 1-4 of the iteration.
+//  1. V_i = V^ie + V_H[n_i] + v_xc(n_i) + v_vW[n_i]
+//  2. Newton search of mu with N(mu) = int c_n I_{1/2}((mu - V_i)/kT) = N_e
+//     (eq. newtonmu), safeguarded by bisection in [min V_i, max V_i] + kT eta_0
+//  3. n_a, dn = n_i - n_a, and the reductions K, ||dn||, ||n_a||, U_xc, max|dn|/n_a
+//  4. convergence test and the More switch
+// Every block reduces the per-block partials of all blocks in the same order,
+// so every block holds bit-identical scalars and takes the same branches.
+__global__ void __launch_bounds__(ARCHE_BLOCK) k_scf_active(ActiveArgs a) {
+  __shared__ double sh[ARCHE_BLOCK / 64];
+  ScfState* st = a.st;
+  if (st->done) return;
+  const unsigned nb = gridDim.x;
+  const int64_t stride = (int64_t)nb * blockDim.x;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+
+  // 1. potential assembly
+  double vmin = INFINITY, vmax = -INFINITY, vsum = 0.0;
+  for (int64_t i = i0; i < a.ng; i += stride) {
+    double n = a.n_i[i];
+    double v = a.Vie[i] + a.VH[i];
+    if (a.xc) {
+      double vxc;
+      lda_xc(n, vxc);
+      v += vxc;
+    }
+    if (a.lam != 0.0) v += -0.5 * a.lam * a.lap_i[i] / sqrt(n);
+    a.Vi[i] = v;
+    vmin = fmin(vmin, v);
+    vmax = fmax(vmax, v);
+    vsum += v;
+  }
+  {
+    double s = block_sum(vsum, sh);
+    put_slot(a.part, 0, nb, s);
+    double m = block_max(vmax, sh);
+    put_slot(a.part, 1, nb, m);
+    double q = block_max(-vmin, sh);
+    put_slot(a.part, 2, nb, q);
+  }
+  grid_barrier(a.bar, a.bar + 1, nb, a.err);
+  const double Vsum = reduce_slot_sum(a.part, 0, nb, sh);
+  const double Vmax = reduce_slot_max(a.part, 1, nb, sh);
+  const double Vmin = -reduce_slot_max(a.part, 2, nb, sh);
+  const double kT = a.kT;
+  double lo = Vmin + kT * a.eta0;
+  double hi = Vmax + kT * a.eta0;
+  double mu = st->mu;
+  if (!(lo <= mu && mu <= hi)) mu = Vsum / (double)a.ng + kT * a.eta0;
+
+  // 2. Newton search of mu
+  int it;
+  bool found = false;
+  double N = 0.0, dN = 0.0;
+  for (it = 1; it <= a.max_newton; ++it) {
+    double s12 = 0.0, sm12 = 0.0;
+    for (int64_t i = i0; i < a.ng; i += stride) {
+      double im, ip;
+      fd_m12_p12(a.fdt, (mu - a.Vi[i]) / kT, im, ip);
+      s12 += ip;
+      sm12 += im;
+    }
+    const int slot = 3 + 2 * (it & 1);
+    double b12 = block_sum(s12, sh);
+    put_slot(a.part, slot, nb, b12);
+    double bm12 = block_sum(sm12, sh);
+    put_slot(a.part, slot + 1, nb, bm12);
+    grid_barrier(a.bar, a.bar + 1, nb, a.err);
+    N = a.dv * a.cn * reduce_slot_sum(a.part, slot, nb, sh);
+    dN = a.dv * a.cn / (2.0 * kT) * reduce_slot_sum(a.part, slot + 1, nb, sh);
+    const double f = N - a.Ne;
+    if (fabs(f) <= 1e-14 * a.Ne) {
+      found = true;
+      break;
+    }
+    if (f > 0.0)
+      hi = mu;
+    else
+      lo = mu;
+    double mn = mu - f / dN;
+    if (!(lo < mn && mn < hi)) mn = 0.5 * (lo + hi);
+    if (fabs(mn - mu) <= 1e-15 * (fabs(mu) + kT)) {
+      mu = mn;
+      found = true;
+      break;
+    }
+    mu = mn;
+  }
+  if (it > a.max_newton) it = a.max_newton;
+
+  // 3. active density and the mixing reductions
+  double sdd = 0.0, snn = 0.0, sK = 0.0, sU = 0.0, sNa = 0.0, smax = 0.0;
+  const double cchi = a.cn / (2.0 * kT);
+  for (int64_t i = i0; i < a.ng; i += stride) {
+    double im, ip;
+    fd_m12_p12(a.fdt, (mu - a.Vi[i]) / kT, im, ip);
+    const double na = a.cn * ip;
+    const double chi = cchi * im;
+    const double ni = a.n_i[i];
+    const double d = ni - na;
+    a.n_a[i] = na;
+    sdd += d * d;
+    snn += na * na;
+    sK += d * d / chi;
+    sNa += na;
+    if (a.xc) {
+      double vi, va;
+      lda_xc(ni, vi);
+      lda_xc(na, va);
+      sU += (vi - va) * d;
+    }
+    smax = fmax(smax, fabs(d) / na);
+  }
+  {
+    double v;
+    v = block_sum(sdd, sh);
+    put_slot(a.part, 7, nb, v);
+    v = block_sum(snn, sh);
+    put_slot(a.part, 8, nb, v);
+    v = block_sum(sK, sh);
+    put_slot(a.part, 9, nb, v);
+    v = block_sum(sU, sh);
+    put_slot(a.part, 10, nb, v);
+    v = block_sum(sNa, sh);
+    put_slot(a.part, 11, nb, v);
+    v = block_max(smax, sh);
+    put_slot(a.part, 12, nb, v);
+  }
+  grid_barrier(a.bar, a.bar + 1, nb, a.err);
+  const double DD = reduce_slot_sum(a.part, 7, nb, sh);
+  const double NN = reduce_slot_sum(a.part, 8, nb, sh);
+  const double KK = reduce_slot_sum(a.part, 9, nb, sh);
+  const double UU = reduce_slot_sum(a.part, 10, nb, sh);
+  const double NA = reduce_slot_sum(a.part, 11, nb, sh);
+  const double MX = reduce_slot_max(a.part, 12, nb, sh);
+
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const double res = sqrt(DD / NN);
+    const int t = st->iter;
+    int more = st->more_on;
+    if (a.mixing == ARCHE_MIX_MORE && !more && t >= a.warmup && MX <= a.trust) more = 1;
+    st->mu = mu;
+    st->N = N;
+    st->dN = dN;
+    st->res = res;
+    st->K = a.dv * KK;
+    st->Uxc = a.dv * UU;
+    st->Na = a.dv * NA;
+    st->maxrel = MX;
+    st->newton_last = it;
+    st->newton_total += it;
+    st->iter = t + 1;
+    st->more_on = more;
+    if (!found) st->mu_fail = 1;
+    const bool bad = !(res == res) || !found || *a.err;
+    if (bad) st->err = 1;
+    st->done = (res < a.tol) || bad;
+  }
+}
+
+// U_vW = int (v_vW[n_i] - v_vW[n_a]) (n_i - n_a), v_vW[n] = -(lambda/2) lap(sqrt n)/sqrt n
+__global__ void __launch_bounds__(ARCHE_BLOCK)
+k_uvw_partial(const ScfState* st, const double* n_i, const double* lap_i, const double* n_a,
+              const double* lap_a, int64_t ng, double lam, double* part) {
+  __shared__ double sh[ARCHE_BLOCK / 64];
+  if (st->done || !st->more_on) return;
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ng; i += (int64_t)gridDim.x * blockDim.x) {
+    const double ni = n_i[i], na = n_a[i];
+    const double vi = -0.5 * lam * lap_i[i] / sqrt(ni);
+    const double va = -0.5 * lam * lap_a[i] / sqrt(na);
+    s += (vi - va) * (ni - na);
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__device__ inline void half_index(int64_t m, int Ny, int Nh, int& ix, int& iy, int& iz) {
+  iz = (int)(m % Nh);
+  int64_t r = m / Nh;
+  iy = (int)(r % Ny);
+  ix = (int)(r / Ny);
+}
+
+__device__ inline double box_k(int i, int N, double L) { return (double)(i <= N / 2 ? i : i - N) / L; }
+
+// sum over the full box of |dn^|^2/(pi k^2) from the half spectrum (mirror terms doubled)
+__global__ void __launch_bounds__(ARCHE_BLOCK)
+k_uh_partial(const ScfState* st, const cplx* nhat_i, const cplx* nhat_a, GridInfo g, double* part) {
+  __shared__ double sh[ARCHE_BLOCK / 64];
+  if (st->done) return;
+  double s = 0.0;
+  for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < g.nh; m += (int64_t)gridDim.x * blockDim.x) {
+    int ix, iy, iz;
+    half_index(m, g.N[1], g.Nh, ix, iy, iz);
+    const double kx = box_k(ix, g.N[0], g.L[0]), ky = box_k(iy, g.N[1], g.L[1]), kz = (double)iz / g.L[2];
+    const double k2 = kx * kx + ky * ky + kz * kz;
+    if (k2 == 0.0) continue;
+    const cplx d = csub(nhat_i[m], nhat_a[m]);
+    const double wgt = (iz == 0 || 2 * iz == g.N[2]) ? 1.0 : 2.0;
+    s += wgt * (d.x * d.x + d.y * d.y) / (PI * k2);
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// Mixing weight (Sec. 2.5.2): w = U/(U+K) with U = U_H + U_xc + U_vW once the More
+// weight is on, else w_fixed; clamped to [0, 0.995].
+__global__ void __launch_bounds__(ARCHE_BLOCK)
+k_mix_weight(ScfState* st, const double* part_h, int nbh, const double* part_v, int nbv, int use_vw,
+             double vol, double dv, double w_fixed) {
+  __shared__ double sh[ARCHE_BLOCK / 64];
+  if (st->done) return;
+  double a = 0.0, b = 0.0;
+  for (int t = threadIdx.x; t < nbh; t += blockDim.x) a += part_h[t];
+  a = block_sum(a, sh);
+  if (use_vw && st->more_on)
+    for (int t = threadIdx.x; t < nbv; t += blockDim.x) b += part_v[t];
+  b = block_sum(b, sh);
+  if (threadIdx.x == 0) {
+    st->UH = a / vol;
+    st->Uvw = (use_vw && st->more_on) ? dv * b : 0.0;
+    double w = w_fixed;
+    if (st->more_on) {
+      const double U = st->UH + st->Uxc + st->Uvw;
+      w = U / (U + st->K);
+      w = fmin(fmax(w, 0.0), 0.995);
+      if (!(w == w)) w = w_fixed;
+    }
+    st->w = w;
+  }
+}
+
+// n^_o = n^_a + w (n^_i - n^_a) -> nhat_i;  tmp = n^_o / (pi k^2) (0 at k = 0)
+__global__ void __launch_bounds__(ARCHE_BLOCK)
+k_spec_mix(const ScfState* st, cplx* nhat_i, const cplx* nhat_a, cplx* tmp, GridInfo g) {
+  if (st->done) return;
+  const double w = st->w;
+  for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < g.nh; m += (int64_t)gridDim.x * blockDim.x) {
+    int ix, iy, iz;
+    half_index(m, g.N[1], g.Nh, ix, iy, iz);
+    const double kx = box_k(ix, g.N[0], g.L[0]), ky = box_k(iy, g.N[1], g.L[1]), kz = (double)iz / g.L[2];
+    const double k2 = kx * kx + ky * ky + kz * kz;
+    const cplx a = nhat_a[m];
+    const cplx o = cadd(a, cscale(csub(nhat_i[m], a), w));
+    nhat_i[m] = o;
+    tmp[m] = k2 > 0.0 ? cscale(o, 1.0 / (PI * k2)) : cplx{0.0, 0.0};
+  }
+}
+
+// n_o = n_a + w (n_i - n_a) -> n_i;  sq = sqrt(n_o)
+__global__ void __launch_bounds__(ARCHE_BLOCK)
+k_real_mix(const ScfState* st, double* n_i, const double* n_a, double* sq, int64_t ng) {
+  if (st->done) return;
+  const double w = st->w;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ng; i += (int64_t)gridDim.x * blockDim.x) {
+    const double na = n_a[i];
+    const double no = na + w * (n_i[i] - na);
+    n_i[i] = no;
+    sq[i] = sqrt(no);
+  }
+}
+
+__global__ void __launch_bounds__(ARCHE_BLOCK)
+k_sqrt(const ScfState* st, int need_more, const double* in, double* out, int64_t ng) {
+  if (st && (st->done || (need_more && !st->more_on))) return;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ng; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = sqrt(in[i]);
+}
+
+// s^ -> -(2 pi |k|)^2 s^
+__global__ void __launch_bounds__(ARCHE_BLOCK) k_spec_lap(cplx* s, GridInfo g) {
+  for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < g.nh; m += (int64_t)gridDim.x * blockDim.x) {
+    int ix, iy, iz;
+    half_index(m, g.N[1], g.Nh, ix, iy, iz);
+    const double kx = box_k(ix, g.N[0], g.L[0]), ky = box_k(iy, g.N[1], g.L[1]), kz = (double)iz / g.L[2];
+    const double q2 = 4.0 * PI * PI * (kx * kx + ky * ky + kz * kz);
+    s[m] = cscale(s[m], -q2);
+  }
+}
+
+// n^ -> n^/(pi k^2), 0 at k = 0 (Hartree, Sec. 2.3)
+__global__ void __launch_bounds__(ARCHE_BLOCK) k_spec_hartree(const cplx* nhat, cplx* out, GridInfo g) {
+  for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < g.nh; m += (int64_t)gridDim.x * blockDim.x) {
+    int ix, iy, iz;
+    half_index(m, g.N[1], g.Nh, ix, iy, iz);
+    const double kx = box_k(ix, g.N[0], g.L[0]), ky = box_k(iy, g.N[1], g.L[1]), kz = (double)iz / g.L[2];
+    const double k2 = kx * kx + ky * ky + kz * kz;
+    out[m] = k2 > 0.0 ? cscale(nhat[m], 1.0 / (PI * k2)) : cplx{0.0, 0.0};
+  }
+}
+
+// Energy sums at the converged (eta = (mu - V_i)/kT, n_a) of Sec. 2.6:
+// 0 sum f0, 1 sum p0, 2 sum n eps_xc, 3 sum n (v_xc - eps_xc), 4 sum n V^ie, 5 sum n
+__global__ void __launch_bounds__(ARCHE_BLOCK)
+k_energy_real(const ScfState* st, const double* Vi, const double* Vie, const FdTables* fdt, int64_t ng,
+              double kT, double cn, double pc, int xc, double* part) {
+  __shared__ double sh[ARCHE_BLOCK / 64];
+  const double mu = st->mu;
+  double s[6] = {0, 0, 0, 0, 0, 0};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ng; i += (int64_t)gridDim.x * blockDim.x) {
+    const double eta = (mu - Vi[i]) / kT;
+    const double ip = fd_eval_order(fdt, 1, eta);
+    const double i32 = fd_eval_order(fdt, 2, eta);
+    const double n = cn * ip;
+    const double p0 = pc * i32;
+    s[0] += n * kT * eta - p0;
+    s[1] += p0;
+    if (xc) {
+      double v;
+      const double e = lda_xc(n, v);
+      s[2] += n * e;
+      s[3] += n * (v - e);
+    }
+    s[4] += n * Vie[i];
+    s[5] += n;
+  }
+  for (int q = 0; q < 6; ++q) {
+    double v = block_sum(s[q], sh);
+    if (threadIdx.x == 0) part[q * gridDim.x + blockIdx.x] = v;
+  }
+}
+
+// sum over the full box of w(k) |f^(k)|^2 with w = 1/(pi k^2) (kind 0) or (2 pi k)^2 (kind 1)
+__global__ void __launch_bounds__(ARCHE_BLOCK)
+k_spec_norm(const cplx* f, GridInfo g, int kind, double* part) {
+  __shared__ double sh[ARCHE_BLOCK / 64];
+  double s = 0.0;
+  for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < g.nh; m += (int64_t)gridDim.x * blockDim.x) {
+    int ix, iy, iz;
+    half_index(m, g.N[1], g.Nh, ix, iy, iz);
+    const double kx = box_k(ix, g.N[0], g.L[0]), ky = box_k(iy, g.N[1], g.L[1]), kz = (double)iz / g.L[2];
+    const double k2 = kx * kx + ky * ky + kz * kz;
+    if (k2 == 0.0) continue;
+    const double wgt = (iz == 0 || 2 * iz == g.N[2]) ? 1.0 : 2.0;
+    const double a2 = f[m].x * f[m].x + f[m].y * f[m].y;
+    s += wgt * a2 * (kind == 0 ? 1.0 / (PI * k2) : 4.0 * PI * PI * k2);
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(ARCHE_BLOCK) k_finish_sums(const double* part, int nblk, int nsum, double* out) {
+  __shared__ double sh[ARCHE_BLOCK / 64];
+  for (int q = 0; q < nsum; ++q) {
+    double v = 0.0;
+    for (int t = threadIdx.x; t < nblk; t += blockDim.x) v += part[(size_t)q * nblk + t];
+    v = block_sum(v, sh);
+    if (threadIdx.x == 0) out[q] = v;
+  }
+}
+
+__global__ void __launch_bounds__(ARCHE_BLOCK) k_fill(double* x, int64_t n, double v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) x[i] = v;
+}
+
+__global__ void k_state_init(ScfState* st, unsigned* bar, int* err, double mu0) {
+  ScfState z{};
+  z.mu = mu0;
+  *st = z;
+  bar[0] = 0;
+  bar[1] = 0;
+  *err = 0;
+}
+
+unsigned grid_for(int64_t n) {
+  int64_t b = (n + ARCHE_BLOCK - 1) / ARCHE_BLOCK;
+  if (b > 2048) b = 2048;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+#define HIP_TRY(x)                         \
+  do {                                     \
+    hipError_t e_ = (x);                   \
+    if (e_ != hipSuccess) return e_;       \
+  } while (0)
+
+}  // namespace
+
+int red_blocks(int64_t n) {
+  int64_t b = (n + 4 * ARCHE_BLOCK - 1) / (4 * ARCHE_BLOCK);
+  if (b > 1024) b = 1024;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+hipError_t finish_sums(const double* partials, int nblk, int nsum, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish_sums, dim3(1), dim3(ARCHE_BLOCK), 0, s, partials, nblk, nsum, out);
+  return hipGetLastError();
+}
+
+// Fermi-Dirac tables: one upload per device, kept for the life of the process.
+const FdTables* fd_tables_device(int device) {
+  static std::mutex mtx;
+  static FdTables* per_dev[64] = {nullptr};
+  if (device < 0 || device >= 64) return nullptr;
+  std::lock_guard<std::mutex> lk(mtx);
+  if (!per_dev[device]) {
+    FdTables h;
+    for (int j = 0; j < 3; ++j) {
+      for (int k = 0; k < FD_KSER; ++k) h.ser[j][k] = FD_SER[j][k];
+      for (int k = 0; k < FD_KASY; ++k) h.asy[j][k] = FD_ASY[j][k];
+      for (int i = 0; i < FD_NINT; ++i)
+        for (int k = 0; k < FD_NCOEF; ++k) h.poly[j][i][k] = FD_POLY[j][i][k];
+    }
+    FdTables* d = nullptr;
+    if (hipMalloc(&d, sizeof(FdTables)) != hipSuccess) return nullptr;
+    if (hipMemcpy(d, &h, sizeof(FdTables), hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+    per_dev[device] = d;
+  }
+  return per_dev[device];
+}
+
+hipError_t scf_reset_state(arche_ctx* c, double mu0) {
+  hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, c->stream, c->state, c->bar, c->err_d, mu0);
+  return hipGetLastError();
+}
+
+// lap = del^2 sqrt(n) through the spectral Laplacian: inverse(-(2 pi k)^2 forward(sqrt n))
+hipError_t scf_vw_laplacian(arche_ctx* c, const double* n, double* lap) {
+  const GridInfo& g = c->g;
+  hipLaunchKernelGGL(k_sqrt, dim3(grid_for(g.ng)), dim3(ARCHE_BLOCK), 0, c->stream, (const ScfState*)nullptr, 0, n,
+                     c->rtmp, g.ng);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(fft_r2c(&c->plan, c->rtmp, c->ctmp, 1.0, g.dv, c->stream));
+  hipLaunchKernelGGL(k_spec_lap, dim3(grid_for(g.nh)), dim3(ARCHE_BLOCK), 0, c->stream, c->ctmp, g);
+  HIP_TRY(hipGetLastError());
+  return fft_c2r(&c->plan, c->ctmp, lap, 1.0 / g.vol, c->stream);
+}
+
+// From the input density n_i: n^_i, V_H[n_i], lap(sqrt n_i).
+static hipError_t prepare_input(arche_ctx* c) {
+  const GridInfo& g = c->g;
+  HIP_TRY(fft_r2c(&c->plan, c->n_i, c->nhat_i, 1.0, g.dv, c->stream));
+  hipLaunchKernelGGL(k_spec_hartree, dim3(grid_for(g.nh)), dim3(ARCHE_BLOCK), 0, c->stream, c->nhat_i, c->ctmp, g);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(fft_c2r(&c->plan, c->ctmp, c->VH, 1.0 / g.vol, c->stream));
+  if (c->p.lambda_vw != 0.0) return scf_vw_laplacian(c, c->n_i, c->lap_i);
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(g.ng)), dim3(ARCHE_BLOCK), 0, c->stream, c->lap_i, g.ng, 0.0);
+  return hipGetLastError();
+}
+
+hipError_t scf_initial_uniform(arche_ctx* c) {
+  const GridInfo& g = c->g;
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(g.ng)), dim3(ARCHE_BLOCK), 0, c->stream, c->n_i, g.ng, c->Ne / g.vol);
+  HIP_TRY(hipGetLastError());
+  return prepare_input(c);
+}
+
+hipError_t scf_prepare_input(arche_ctx* c) { return prepare_input(c); }
+
+// Blocks of the cooperative SCF launch: all co-resident, at most two per CU, and
+// no more than the grid needs.  Fixed for a given device and grid, so the
+// reduction order (and the result) is reproducible.
+int scf_coop_blocks(int64_t ng) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_scf_active, ARCHE_BLOCK, 0) != hipSuccess) return 0;
+  int64_t b = std::min<int64_t>((int64_t)per_cu * cus, 2 * (int64_t)cus);
+  b = std::min<int64_t>(b, (ng + 4 * ARCHE_BLOCK - 1) / (4 * ARCHE_BLOCK));
+  return (int)std::max<int64_t>(b, 1);
+}
+
+hipError_t scf_iteration(arche_ctx* c) {
+  const GridInfo& g = c->g;
+  const arche_params& p = c->p;
+  ActiveArgs a;
+  a.Vie = c->Vie;
+  a.VH = c->VH;
+  a.lap_i = c->lap_i;
+  a.n_i = c->n_i;
+  a.Vi = c->Vi;
+  a.n_a = c->n_a;
+  a.st = c->state;
+  a.part = c->partials;
+  a.bar = c->bar;
+  a.err = c->err_d;
+  a.fdt = c->fdt;
+  a.ng = g.ng;
+  a.dv = g.dv;
+  a.kT = p.kT;
+  a.cn = std::pow(2.0 * p.kT, 1.5) / (2.0 * PI * PI);
+  a.Ne = c->Ne;
+  a.lam = p.lambda_vw;
+  a.xc = p.xc;
+  a.eta0 = c->eta0;
+  a.tol = p.scf_tol;
+  a.mixing = p.mixing;
+  a.warmup = p.more_warmup;
+  a.trust = p.more_trust;
+  a.max_newton = 200;
+  void* args[] = {&a};
+  HIP_TRY(hipLaunchCooperativeKernel((const void*)k_scf_active, dim3(c->coop_blocks), dim3(ARCHE_BLOCK), args, 0,
+                                     c->stream));
+  // n^_a
+  HIP_TRY(fft_r2c(&c->plan, c->n_a, c->nhat_a, 1.0, g.dv, c->stream));
+  const bool vw = p.lambda_vw != 0.0;
+  const bool more = p.mixing == ARCHE_MIX_MORE;
+  const int nbr = red_blocks(g.ng);
+  const int nbh = red_blocks(g.nh);
+  double* part_h = c->partials + 16 * (size_t)c->coop_blocks;
+  double* part_v = part_h + nbh;
+  if (more && vw) {
+    // lap(sqrt n_a) for the von Weizsaecker part of U
+    hipLaunchKernelGGL(k_sqrt, dim3(grid_for(g.ng)), dim3(ARCHE_BLOCK), 0, c->stream, (const ScfState*)c->state, 1,
+                       c->n_a, c->rtmp, g.ng);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(fft_r2c(&c->plan, c->rtmp, c->ctmp, 1.0, g.dv, c->stream));
+    hipLaunchKernelGGL(k_spec_lap, dim3(grid_for(g.nh)), dim3(ARCHE_BLOCK), 0, c->stream, c->ctmp, g);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(fft_c2r(&c->plan, c->ctmp, c->lap_a, 1.0 / g.vol, c->stream));
+    hipLaunchKernelGGL(k_uvw_partial, dim3(nbr), dim3(ARCHE_BLOCK), 0, c->stream, (const ScfState*)c->state, c->n_i,
+                       c->lap_i, c->n_a, c->lap_a, g.ng, p.lambda_vw, part_v);
+    HIP_TRY(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_uh_partial, dim3(nbh), dim3(ARCHE_BLOCK), 0, c->stream, (const ScfState*)c->state, c->nhat_i,
+                     c->nhat_a, g, part_h);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_mix_weight, dim3(1), dim3(ARCHE_BLOCK), 0, c->stream, c->state, part_h, nbh, part_v, nbr,
+                     (int)(more && vw), g.vol, g.dv, p.w_fixed);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_spec_mix, dim3(grid_for(g.nh)), dim3(ARCHE_BLOCK), 0, c->stream, (const ScfState*)c->state,
+                     c->nhat_i, c->nhat_a, c->ctmp, g);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(fft_c2r(&c->plan, c->ctmp, c->VH, 1.0 / g.vol, c->stream));
+  hipLaunchKernelGGL(k_real_mix, dim3(grid_for(g.ng)), dim3(ARCHE_BLOCK), 0, c->stream, (const ScfState*)c->state,
+                     c->n_i, c->n_a, c->rtmp, g.ng);
+  HIP_TRY(hipGetLastError());
+  if (vw) {
+    HIP_TRY(fft_r2c(&c->plan, c->rtmp, c->ctmp, 1.0, g.dv, c->stream));
+    hipLaunchKernelGGL(k_spec_lap, dim3(grid_for(g.nh)), dim3(ARCHE_BLOCK), 0, c->stream, c->ctmp, g);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(fft_c2r(&c->plan, c->ctmp, c->lap_i, 1.0 / g.vol, c->stream));
+  }
+  return hipSuccess;
+}
+
+// out: 0 F_TF, 1 K_e, 2 F_xc, 3 P_xc, 4 int n V^ie, 5 int n, 6 E_H, 7 F_vW, 8 P_TF
+hipError_t scf_energies(arche_ctx* c, double* out) {
+  const GridInfo& g = c->g;
+  const arche_params& p = c->p;
+  const double cn = std::pow(2.0 * p.kT, 1.5) / (2.0 * PI * PI);
+  const double pc = (2.0 * std::sqrt(2.0) / (3.0 * PI * PI)) * std::pow(p.kT, 2.5);
+  const int nbr = red_blocks(g.ng);
+  hipLaunchKernelGGL(k_energy_real, dim3(nbr), dim3(ARCHE_BLOCK), 0, c->stream, (const ScfState*)c->state, c->Vi,
+                     c->Vie, c->fdt, g.ng, p.kT, cn, pc, p.xc, c->partials);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(finish_sums(c->partials, nbr, 6, c->sums, c->stream));
+  HIP_TRY(fft_r2c(&c->plan, c->n_a, c->nhat_a, 1.0, g.dv, c->stream));
+  const int nbh = red_blocks(g.nh);
+  double* part2 = c->partials + 6 * (size_t)nbr;
+  hipLaunchKernelGGL(k_spec_norm, dim3(nbh), dim3(ARCHE_BLOCK), 0, c->stream, (const cplx*)c->nhat_a, g, 0, part2);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(finish_sums(part2, nbh, 1, c->sums + 6, c->stream));
+  if (p.lambda_vw != 0.0) {
+    hipLaunchKernelGGL(k_sqrt, dim3(grid_for(g.ng)), dim3(ARCHE_BLOCK), 0, c->stream, (const ScfState*)nullptr, 0,
+                       c->n_a, c->rtmp, g.ng);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(fft_r2c(&c->plan, c->rtmp, c->ctmp, 1.0, g.dv, c->stream));
+    double* part3 = part2 + nbh;
+    hipLaunchKernelGGL(k_spec_norm, dim3(nbh), dim3(ARCHE_BLOCK), 0, c->stream, (const cplx*)c->ctmp, g, 1, part3);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(finish_sums(part3, nbh, 1, c->sums + 7, c->stream));
+  }
+  double h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  HIP_TRY(hipMemcpyAsync(h, c->sums, 8 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  out[0] = g.dv * h[0];
+  out[1] = 1.5 * g.dv * h[1];
+  out[2] = g.dv * h[2];
+  out[3] = h[3] / (double)g.ng;
+  out[4] = g.dv * h[4];
+  out[5] = g.dv * h[5];
+  out[6] = 0.5 * h[6] / g.vol;
+  out[7] = p.lambda_vw != 0.0 ? 0.5 * p.lambda_vw * h[7] / g.vol : 0.0;
+  out[8] = h[1] / (double)g.ng;
+  return hipSuccess;
+}

@@ -63,13 +63,15 @@ def fcc_positions(cells: int, L: float) -> np.ndarray:
     return np.array(pts, dtype=np.float64)
 
 
-def random_positions(n: int, L: float, dmin: float, rng: np.random.Generator) -> np.ndarray:
-    """Uniform positions in [0, L)^3, rejecting any closer than dmin (minimum image)."""
+def random_positions(n: int, L, dmin: float, rng: np.random.Generator) -> np.ndarray:
+    """Uniform positions in the cell [0, L) (L a scalar or three edges), rejecting
+    any closer than dmin to an earlier one (minimum image)."""
+    L = np.broadcast_to(np.asarray(L, dtype=np.float64), (3,))
     pos = np.empty((n, 3))
     k = 0
     tries = 0
     while k < n:
-        p = rng.uniform(0.0, L, 3)
+        p = rng.uniform(0.0, 1.0, 3) * L
         if k:
             d = pos[:k] - p
             d -= L * np.round(d / L)
@@ -120,6 +122,7 @@ class Workload:
     lam: float = 0.2
     xc: bool = True
     seed: int = 0
+    w_fixed: float = 0.95  # fixed mixing weight before More's weight switches on
 
     def __post_init__(self):
         if self.species is None:
@@ -131,7 +134,7 @@ def fcc32(seed: int = 1) -> Workload:
     rng = np.random.default_rng(seed)
     pos = fcc_positions(2, L) + rng.normal(0.0, 0.05 / BOHR_ANGSTROM, size=(32, 3))
     return Workload("fcc32_32^3_1eV", (L, L, L), (32, 32, 32), pos, ev(1.0),
-                    vel=np.zeros((32, 3)), steps=1, seed=seed)
+                    vel=np.zeros((32, 3)), steps=1, seed=seed, w_fixed=0.99)
 
 
 def fcc256(seed: int = 2, steps: int = 50) -> Workload:
@@ -166,14 +169,15 @@ def rand1024(seed: int = 5, steps: int = 100) -> Workload:
     kT = ev(10.0)
     vel = mb_velocities(1024, kT, AL_MASS, rng)
     return Workload("rand1024_128^3_10eV", (L, L, L), (128, 128, 128), pos, kT, vel=vel,
-                    steps=steps, seed=seed)
+                    steps=steps, seed=seed, w_fixed=0.97)
 
 
 def rand4000(seed: int = 6) -> Workload:
     L = cell_length(4000, 2.7)
     rng = np.random.default_rng(seed)
     pos = random_positions(4000, L, 1.0 / BOHR_ANGSTROM, rng)
-    return Workload("rand4000_192^3_10eV", (L, L, L), (192, 192, 192), pos, ev(10.0), seed=seed)
+    return Workload("rand4000_192^3_10eV", (L, L, L), (192, 192, 192), pos, ev(10.0), seed=seed,
+                    w_fixed=0.98)
 
 
 def small_random(n_atoms: int, N: int, rho: float, T_ev: float, seed: int,
@@ -182,7 +186,7 @@ def small_random(n_atoms: int, N: int, rho: float, T_ev: float, seed: int,
     L = cell_length(n_atoms, rho)
     cell = tuple(L * s for s in stretch)
     rng = np.random.default_rng(seed)
-    pos = rng.uniform(0.0, 1.0, size=(n_atoms, 3)) * np.array(cell)
+    pos = random_positions(n_atoms, cell, 1.0 / BOHR_ANGSTROM, rng)
     grid = shape if shape is not None else (N, N, N)
     return Workload("rand%d_%s_%geV" % (n_atoms, "x".join(map(str, grid)), T_ev), cell, grid, pos,
                     ev(T_ev), vel=np.zeros((n_atoms, 3)), seed=seed)

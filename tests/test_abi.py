@@ -1,0 +1,94 @@
+"""Host-side checks of the C ABI (no GPU needed): the library builds, loads and
+exports every entry point include/*.h declares; the ctypes structs match the C
+layout; parameter validation rejects bad input before touching a device."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2606_13283_amd import arche
+from paper_2606_13283_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+INC = os.path.join(ROOT, "include")
+
+
+def declared_functions():
+    names = set()
+    for h in os.listdir(INC):
+        if h.endswith(".h"):
+            text = open(os.path.join(INC, h)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(arche_\w+)\s*\(", text))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(arche.LIB_PATH):
+        from paper_2606_13283_amd import build
+        build.build()
+    return arche.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_struct_layout_matches_c(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text("""
+#include <stdio.h>
+#include <stddef.h>
+#include "arche.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(arche_params), offsetof(arche_params, cell),
+         offsetof(arche_params, kT), offsetof(arche_params, init), sizeof(arche_result),
+         offsetof(arche_result, scf_iters));
+  return 0;
+}
+""")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", INC, str(src), "-o", str(exe)], check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    P, R = arche.Params, arche.Result
+    assert vals == [ctypes.sizeof(P), P.cell.offset, P.kT.offset, P.init.offset, ctypes.sizeof(R),
+                    R.scf_iters.offset]
+
+
+def _params(**kw):
+    w = W.fcc32()
+    d = dict(cell=w.cell, grid=w.grid, species=w.species, Z=w.Z, rc=w.rc, mass=w.mass, kT=w.kT)
+    d.update(kw)
+    return d
+
+
+@pytest.mark.parametrize("bad", [dict(grid=(32, 32, 33)), dict(grid=(32, 32, 14 * 2 * 7)), dict(kT=-1.0),
+                                 dict(species=np.full(32, 3)), dict(cell=(15.0, 0.0, 15.0)),
+                                 dict(Z=(-3.0,)), dict(grid=(2048, 32, 32))])
+def test_invalid_parameters_rejected_on_host(lib, bad):
+    with pytest.raises(arche.ArcheError) as e:
+        arche.Context(**_params(**bad))
+    assert e.value.status == arche.EINVAL
+    assert lib.arche_last_error(None).decode() != ""
+
+
+def test_invalid_options_rejected(lib):
+    for o in (arche.Options(scf_tol=0.0), arche.Options(w_fixed=1.0), arche.Options(mixing=7),
+              arche.Options(scf_max_iter=0), arche.Options(init=9)):
+        with pytest.raises(arche.ArcheError) as e:
+            arche.Context(**_params(), opts=o)
+        assert e.value.status == arche.EINVAL
+
+
+def test_null_handles(lib):
+    assert lib.arche_scf_init(None, None, None) == arche.EINVAL
+    assert lib.arche_forces(None, None) == arche.EINVAL
+    lib.arche_scf_free(None)
+    assert lib.arche_version().decode().startswith("arche")
