@@ -53,6 +53,19 @@ arche_status arche_debug_get(arche_ctx *ctx, int32_t which, double *dst_host);
 arche_status arche_debug_one_center(arche_ctx *ctx, const double *pos_host, double *n_init_host,
                                     int32_t *used_fallback);
 
+/* Per-kernel timing.  When enabled, every launch of the kernels below made by
+ * calls on ctx is bracketed by a pair of hipEvents on the context's stream and
+ * the elapsed times are summed (the events add a few microseconds per launch).
+ *   ARCHE_PROF_SCF_ACTIVE   the cooperative kernel of one SCF iteration
+ *                           (potential, Newton search of mu, active density)
+ *   ARCHE_PROF_FFT_Z        the z passes of the 3D FFTs (R2C and C2R)
+ *   ARCHE_PROF_FFT_STRIDED  the y and x passes of the 3D FFTs */
+enum { ARCHE_PROF_SCF_ACTIVE = 0, ARCHE_PROF_FFT_Z = 1, ARCHE_PROF_FFT_STRIDED = 2 };
+arche_status arche_profile_enable(arche_ctx *ctx, int32_t on);
+arche_status arche_profile_reset(arche_ctx *ctx);
+/* ESTATE unless profiling is enabled; EINVAL for an unknown kind */
+arche_status arche_profile_read(arche_ctx *ctx, int32_t kind, double *total_ms, int64_t *launches);
+
 #ifdef __cplusplus
 }
 #endif

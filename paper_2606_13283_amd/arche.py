@@ -21,6 +21,7 @@ MIX_FIXED, MIX_MORE = 0, 1
 XC_NONE, XC_LDA = 0, 1
 TERM_NAMES = ("F_TF", "K_e", "F_vW", "E_H", "F_xc", "E_ie", "U_ii", "U_pp", "U_pm", "U_je", "alpha")
 PTERM_NAMES = ("P_TF", "P_vW", "P_H", "P_xc", "P_ie", "P_ii")
+PROF_NAMES = ("scf_active", "fft_z", "fft_strided")
 DBG = dict(Vie=0, Vi=1, n_a=2, n_i=3, SZ_plus=4, SZ_minus=5, nhat_a=6, F_pp=7)
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -98,6 +99,12 @@ def load(path: str = LIB_PATH):
     L.arche_debug_get.restype = st
     L.arche_debug_one_center.argtypes = [vp, _dp, _dp, _ip]
     L.arche_debug_one_center.restype = st
+    L.arche_profile_enable.argtypes = [vp, ctypes.c_int32]
+    L.arche_profile_enable.restype = st
+    L.arche_profile_reset.argtypes = [vp]
+    L.arche_profile_reset.restype = st
+    L.arche_profile_read.argtypes = [vp, ctypes.c_int32, _dp, ctypes.POINTER(ctypes.c_int64)]
+    L.arche_profile_read.restype = st
     L.arche_k_fft_r2c.argtypes = [_ip, vp, vp, vp]
     L.arche_k_fft_r2c.restype = st
     L.arche_k_fft_c2r.argtypes = [_ip, vp, vp, vp]
@@ -231,6 +238,21 @@ class Context:
         fb = ctypes.c_int32(0)
         self._check(self._L.arche_debug_one_center(self._h, _ptr(pos), _ptr(out), ctypes.byref(fb)))
         return out, bool(fb.value)
+
+    def profile(self, on=True):
+        self._check(self._L.arche_profile_enable(self._h, 1 if on else 0))
+
+    def profile_reset(self):
+        self._check(self._L.arche_profile_reset(self._h))
+
+    def profile_read(self):
+        out = {}
+        for k, name in enumerate(PROF_NAMES):
+            ms = ctypes.c_double(0.0)
+            n = ctypes.c_int64(0)
+            self._check(self._L.arche_profile_read(self._h, k, ctypes.byref(ms), ctypes.byref(n)))
+            out[name] = (ms.value, n.value)
+        return out
 
     def close(self):
         if getattr(self, "_h", None):

@@ -8,6 +8,7 @@
 #include "../../include/arche.h"
 #include "common.h"
 #include "fft.h"
+#include "profile.h"
 
 // Scalars of the SCF iteration kept on the device (read back by the host only
 // to poll convergence).  Written by the kernels of scf.hip.
@@ -85,7 +86,7 @@ struct arche_ctx {
   double *sums = nullptr;      // small result vectors
   ScfState *state = nullptr;
   ScfState *state_host = nullptr;  // pinned mirror
-  unsigned *bar = nullptr;         // grid barrier count + generation
+  unsigned *bar = nullptr;         // grid all-reduce arrival flags [coop_blocks] + go word
   int *err_d = nullptr;
   const FdTables *fdt = nullptr;
 
@@ -97,6 +98,8 @@ struct arche_ctx {
   // MD state
   std::vector<double> r_prev;
   bool have_r_prev = false;
+  // optional per-kernel timing
+  Profiler* prof = nullptr;
 };
 
 // device Fermi-Dirac tables (uploaded once per process and device)

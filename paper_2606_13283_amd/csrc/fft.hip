@@ -1,5 +1,7 @@
 // FP64 3D real<->complex FFT for gfx950 (see fft.h for the layout and passes).
 #include "fft.h"
+#include "fft_plans.h"
+#include "profile.h"
 
 #include <cmath>
 #include <cstring>
@@ -247,6 +249,225 @@ k_fft_strided(cplx* __restrict__ data, const cplx* __restrict__ tw_g, int L, int
   }
 }
 
+// ---------------------------------------------------------------------------
+// Compile-time kernels (fft_plans.h) for the supported line lengths.
+using namespace fftct;
+
+struct ColIn {  // column tile of a strided pass: element k of column `line`
+  const cplx* base;
+  int64_t es;
+  int nc;
+  __device__ cplx operator()(int line, int k) const { return line < nc ? base[(int64_t)k * es + line] : cplx{0.0, 0.0}; }
+};
+struct ColOut {
+  cplx* base;
+  int64_t es;
+  int nc;
+  double scale;
+  __device__ void operator()(int line, int k, cplx v) const {
+    if (line < nc) base[(int64_t)k * es + line] = cscale(v, scale);
+  }
+  __device__ void barrier_before() const {}
+  __device__ void barrier_after() const {}
+};
+
+template <int L, int TK, int S>
+__global__ void __launch_bounds__(ARCHE_BLOCK)
+k_strided_ct(cplx* __restrict__ data, const cplx* __restrict__ tw_g, int64_t es, int64_t os, int ncols, int nchunk,
+             double scale) {
+  constexpr int NS = nstages(typename Plan<L>::R{});
+  __shared__ cplx lds[NS > 1 ? lds_size<L, TK, true>() : 1];
+  __shared__ cplx tw[L];
+  for (int i = threadIdx.x; i < L; i += ARCHE_BLOCK) tw[i] = tw_g[i];
+  __syncthreads();
+  const int o = blockIdx.x / nchunk;
+  const int c0 = (blockIdx.x - o * nchunk) * TK;
+  const int nc = (ncols - c0) < TK ? (ncols - c0) : TK;
+  cplx* base = data + (int64_t)o * os + c0;
+  run<L, TK, ARCHE_BLOCK, true, S, 1>(ColIn{base, es, nc}, ColOut{base, es, nc, scale}, lds, tw, nc,
+                                       typename Plan<L>::R{});
+}
+
+struct PairIn {  // two real rows packed as one complex line
+  const double* src;
+  int L;
+  int nv;
+  double s;
+  __device__ cplx operator()(int line, int k) const {
+    if (line >= nv) return cplx{0.0, 0.0};
+    const double* r0 = src + (int64_t)line * 2 * L;
+    return cplx{r0[k] * s, r0[L + k] * s};
+  }
+};
+
+template <int L, int B>
+__global__ void __launch_bounds__(ARCHE_BLOCK)
+k_z_r2c_ct(const double* __restrict__ in, cplx* __restrict__ out, const cplx* __restrict__ tw_g, int64_t npairs,
+           double in_scale, double out_scale) {
+  constexpr int Nh = L / 2 + 1;
+  __shared__ cplx lds[lds_size<L, B, false>()];
+  __shared__ cplx tw[L];
+  for (int i = threadIdx.x; i < L; i += ARCHE_BLOCK) tw[i] = tw_g[i];
+  __syncthreads();
+  const int64_t p0 = (int64_t)blockIdx.x * B;
+  const int nb = (int)((npairs - p0) < B ? (npairs - p0) : B);
+  LdsIO<L, B, false> res{lds};
+  run<L, B, ARCHE_BLOCK, false, -1, 1>(PairIn{in + p0 * 2 * L, L, nb, in_scale}, res, lds, tw, nb,
+                                        typename Plan<L>::R{});
+  cplx* dst = out + p0 * 2 * Nh;
+  for (int q = threadIdx.x; q < nb * 2 * Nh; q += ARCHE_BLOCK) {
+    const int l = q / (2 * Nh);
+    const int w = q - l * 2 * Nh;
+    const int r = w / Nh;
+    const int k = w - r * Nh;
+    const cplx zk = res(l, k);
+    const cplx zn = res(l, k == 0 ? 0 : L - k);
+    cplx v;
+    if (r == 0)
+      v = cplx{0.5 * (zk.x + zn.x), 0.5 * (zk.y - zn.y)};
+    else
+      v = cplx{0.5 * (zk.y + zn.y), -0.5 * (zk.x - zn.x)};
+    dst[q] = cscale(v, out_scale);
+  }
+}
+
+struct HermIn {  // Z_k = X_k + i Y_k from the half spectra of two real rows
+  const cplx* src;
+  int L, Nh, nv;
+  __device__ cplx operator()(int line, int k) const {
+    if (line >= nv) return cplx{0.0, 0.0};
+    const cplx* X = src + (int64_t)line * 2 * Nh;
+    const cplx* Y = X + Nh;
+    cplx x, y;
+    if (k == 0 || 2 * k == L) {
+      x = cplx{X[k].x, 0.0};
+      y = cplx{Y[k].x, 0.0};
+    } else if (2 * k < L) {
+      x = X[k];
+      y = Y[k];
+    } else {
+      x = cconj(X[L - k]);
+      y = cconj(Y[L - k]);
+    }
+    return cplx{x.x - y.y, x.y + y.x};
+  }
+};
+struct PairOut {
+  double* dst;
+  int L, nv;
+  double scale;
+  __device__ void operator()(int line, int k, cplx v) const {
+    if (line >= nv) return;
+    double* r0 = dst + (int64_t)line * 2 * L;
+    r0[k] = v.x * scale;
+    r0[L + k] = v.y * scale;
+  }
+  __device__ void barrier_before() const {}
+  __device__ void barrier_after() const {}
+};
+
+template <int L, int B>
+__global__ void __launch_bounds__(ARCHE_BLOCK)
+k_z_c2r_ct(const cplx* __restrict__ in, double* __restrict__ out, const cplx* __restrict__ tw_g, int64_t npairs,
+           double out_scale) {
+  constexpr int Nh = L / 2 + 1;
+  constexpr int NS = nstages(typename Plan<L>::R{});
+  __shared__ cplx lds[NS > 1 ? lds_size<L, B, false>() : 1];
+  __shared__ cplx tw[L];
+  for (int i = threadIdx.x; i < L; i += ARCHE_BLOCK) tw[i] = tw_g[i];
+  __syncthreads();
+  const int64_t p0 = (int64_t)blockIdx.x * B;
+  const int nb = (int)((npairs - p0) < B ? (npairs - p0) : B);
+  run<L, B, ARCHE_BLOCK, false, +1, 1>(HermIn{in + p0 * 2 * Nh, L, Nh, nb}, PairOut{out + p0 * 2 * L, L, nb, out_scale},
+                                        lds, tw, nb, typename Plan<L>::R{});
+}
+
+constexpr int CT_TK = 16;
+template <int L>
+constexpr int ct_rows() {
+  return L >= 96 ? 16 : 32;
+}
+
+template <int L>
+hipError_t launch_strided_ct(cplx* data, const cplx* tw, int64_t es, int64_t os, int nouter, int ncols, int sign,
+                             double scale, hipStream_t s) {
+  const int nchunk = (ncols + CT_TK - 1) / CT_TK;
+  if (sign < 0)
+    hipLaunchKernelGGL((k_strided_ct<L, CT_TK, -1>), dim3(nouter * nchunk), dim3(ARCHE_BLOCK), 0, s, data, tw, es, os,
+                       ncols, nchunk, scale);
+  else
+    hipLaunchKernelGGL((k_strided_ct<L, CT_TK, +1>), dim3(nouter * nchunk), dim3(ARCHE_BLOCK), 0, s, data, tw, es, os,
+                       ncols, nchunk, scale);
+  return hipGetLastError();
+}
+template <int L>
+hipError_t launch_z_r2c_ct(const double* in, cplx* out, const cplx* tw, int64_t npairs, double is, double os,
+                           hipStream_t s) {
+  constexpr int B = ct_rows<L>();
+  hipLaunchKernelGGL((k_z_r2c_ct<L, B>), dim3((unsigned)((npairs + B - 1) / B)), dim3(ARCHE_BLOCK), 0, s, in, out, tw,
+                     npairs, is, os);
+  return hipGetLastError();
+}
+template <int L>
+hipError_t launch_z_c2r_ct(const cplx* in, double* out, const cplx* tw, int64_t npairs, double os, hipStream_t s) {
+  constexpr int B = ct_rows<L>();
+  hipLaunchKernelGGL((k_z_c2r_ct<L, B>), dim3((unsigned)((npairs + B - 1) / B)), dim3(ARCHE_BLOCK), 0, s, in, out, tw,
+                     npairs, os);
+  return hipGetLastError();
+}
+
+// kind 0: strided, 1: z r2c, 2: z c2r.  Returns hipErrorNotSupported for other sizes.
+#define ARCHE_CT_SIZES(X) \
+  X(16) X(20) X(24) X(30) X(32) X(40) X(48) X(50) X(54) X(60) X(64) X(72) X(80) X(96) X(100) X(120) X(128) X(144) \
+  X(160) X(180) X(192) X(256)
+
+bool ct_supported(int L) {
+  switch (L) {
+#define X(n) case n:
+    ARCHE_CT_SIZES(X)
+#undef X
+    return true;
+    default:
+      return false;
+  }
+}
+
+hipError_t ct_strided(int L, cplx* data, const cplx* tw, int64_t es, int64_t os, int nouter, int ncols, int sign,
+                      double scale, hipStream_t s) {
+  switch (L) {
+#define X(n) \
+  case n:    \
+    return launch_strided_ct<n>(data, tw, es, os, nouter, ncols, sign, scale, s);
+    ARCHE_CT_SIZES(X)
+#undef X
+    default:
+      return hipErrorNotSupported;
+  }
+}
+hipError_t ct_z_r2c(int L, const double* in, cplx* out, const cplx* tw, int64_t npairs, double is, double os,
+                    hipStream_t s) {
+  switch (L) {
+#define X(n) \
+  case n:    \
+    return launch_z_r2c_ct<n>(in, out, tw, npairs, is, os, s);
+    ARCHE_CT_SIZES(X)
+#undef X
+    default:
+      return hipErrorNotSupported;
+  }
+}
+hipError_t ct_z_c2r(int L, const cplx* in, double* out, const cplx* tw, int64_t npairs, double os, hipStream_t s) {
+  switch (L) {
+#define X(n) \
+  case n:    \
+    return launch_z_c2r_ct<n>(in, out, tw, npairs, os, s);
+    ARCHE_CT_SIZES(X)
+#undef X
+    default:
+      return hipErrorNotSupported;
+  }
+}
+
 Radices radices_of(const FftAxis& ax) {
   Radices r;
   r.nst = ax.nst;
@@ -275,6 +496,8 @@ hipError_t strided_pass(const FftPlan* p, cplx* data, int axis, int sign, double
     os = Nh;
     nouter = Ny;
   }
+  ProfScope prof(PROF_FFT_STRIDED, s);
+  if (ct_supported(ax.L)) return ct_strided(ax.L, data, ax.tw, es, os, nouter, Nh, sign, scale, s);
   const int TK = strided_tile(ax.L);
   const int nchunk = (Nh + TK - 1) / TK;
   const size_t lds = (size_t)(2 * ax.L * TK + ax.L) * sizeof(cplx);
@@ -284,6 +507,8 @@ hipError_t strided_pass(const FftPlan* p, cplx* data, int axis, int sign, double
 }
 
 }  // namespace
+
+thread_local Profiler* g_profiler = nullptr;
 
 bool fft_size_supported(int n) {
   if (n < 2 || n > 1024 || (n & 1)) return false;
@@ -353,8 +578,15 @@ hipError_t fft_r2c(const FftPlan* p, const double* in, cplx* out, double in_scal
   const int64_t npairs = (int64_t)p->N[0] * p->N[1] / 2;
   const int B = z_rows_per_block(Nz);
   const size_t lds = (size_t)(2 * B * (Nz + 2) + Nz) * sizeof(cplx);
+  {
+  ProfScope prof(PROF_FFT_Z, s);
+  if (ct_supported(Nz)) {
+    hipError_t e0 = ct_z_r2c(Nz, in, out, az.tw, npairs, in_scale, 1.0, s);
+    if (e0 != hipSuccess) return e0;
+  } else
   hipLaunchKernelGGL(k_fft_z_r2c, dim3((unsigned)((npairs + B - 1) / B)), dim3(ARCHE_BLOCK), lds, s, in, out,
                      az.tw, Nz, p->Nh, npairs, B, radices_of(az), in_scale, 1.0);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   e = strided_pass(p, out, 1, -1, 1.0, s);
@@ -372,6 +604,8 @@ hipError_t fft_c2r(const FftPlan* p, cplx* in, double* out, double out_scale, hi
   const int64_t npairs = (int64_t)p->N[0] * p->N[1] / 2;
   const int B = z_rows_per_block(Nz);
   const size_t lds = (size_t)(2 * B * (Nz + 2) + Nz) * sizeof(cplx);
+  ProfScope prof(PROF_FFT_Z, s);
+  if (ct_supported(Nz)) return ct_z_c2r(Nz, in, out, az.tw, npairs, out_scale, s);
   hipLaunchKernelGGL(k_fft_z_c2r, dim3((unsigned)((npairs + B - 1) / B)), dim3(ARCHE_BLOCK), lds, s, in, out,
                      az.tw, Nz, p->Nh, npairs, B, radices_of(az), out_scale);
   return hipGetLastError();

@@ -85,6 +85,8 @@ void free_all(arche_ctx* c) {
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->state_host) (void)hipHostFree(c->state_host);
+  delete c->prof;
+  c->prof = nullptr;
   if (c->plan.ok) fft_plan_destroy(&c->plan);
 }
 
@@ -203,7 +205,18 @@ arche_status evaluate(arche_ctx* c, arche_result* out) {
   return ARCHE_OK;
 }
 
+// installs the context's profiler (if enabled) for the duration of one call
+struct ProfInstall {
+  Profiler* p;
+  explicit ProfInstall(arche_ctx* c) : p(c->prof) { g_profiler = p; }
+  ~ProfInstall() {
+    if (p) p->collect();
+    g_profiler = nullptr;
+  }
+};
+
 arche_status do_solve(arche_ctx* c, const double* pos_host, arche_result* out, int init) {
+  ProfInstall pi(c);
   const int n = c->n_atoms;
   for (int q = 0; q < 3 * n; ++q)
     if (!std::isfinite(pos_host[q])) return set_err(c, ARCHE_EINVAL, "non-finite position");
@@ -238,6 +251,7 @@ arche_status do_solve(arche_ctx* c, const double* pos_host, arche_result* out, i
 }
 
 arche_status do_forces(arche_ctx* c) {
+  ProfInstall pi(c);
   if (!c->forces_ready) {
     CK(ionic_forces(c, c->nhat_a, c->forces));
     c->h_forces.resize(3 * c->n_atoms);
@@ -348,7 +362,7 @@ arche_status arche_scf_init(const arche_params* p, void* hip_stream, arche_ctx**
   ok = ok && dalloc(&c->partials, (size_t)c->partial_cap) == hipSuccess;
   ok = ok && dalloc(&c->sums, 64) == hipSuccess;
   ok = ok && dalloc(&c->state, 1) == hipSuccess;
-  ok = ok && dalloc(&c->bar, 2) == hipSuccess;
+  ok = ok && dalloc(&c->bar, (size_t)c->coop_blocks + 1) == hipSuccess;
   ok = ok && dalloc(&c->err_d, 1) == hipSuccess;
   if (ok) ok = dalloc(&c->fpart, ionic_force_partials(c)) == hipSuccess;
   if (ok) ok = hipHostMalloc((void**)&c->state_host, 2 * sizeof(ScfState), hipHostMallocDefault) == hipSuccess;
@@ -521,6 +535,36 @@ arche_status arche_debug_one_center(arche_ctx* c, const double* pos_host, double
   CK(hipStreamSynchronize(c->stream));
   c->solved = false;
   c->converged = false;
+  return ARCHE_OK;
+}
+
+arche_status arche_profile_enable(arche_ctx* c, int32_t on) {
+  if (!c) return ARCHE_EINVAL;
+  if (on && !c->prof) c->prof = new (std::nothrow) Profiler();
+  if (on && !c->prof) return set_err(c, ARCHE_ENOMEM, "profiler allocation failed");
+  if (!on) {
+    delete c->prof;
+    c->prof = nullptr;
+  }
+  return ARCHE_OK;
+}
+
+arche_status arche_profile_read(arche_ctx* c, int32_t kind, double* total_ms, int64_t* launches) {
+  if (!c || !total_ms || !launches || kind < 0 || kind >= PROF_KINDS) return ARCHE_EINVAL;
+  if (!c->prof) return set_err(c, ARCHE_ESTATE, "profiling is not enabled");
+  *total_ms = c->prof->total_ms[kind];
+  *launches = c->prof->launches[kind];
+  return ARCHE_OK;
+}
+
+arche_status arche_profile_reset(arche_ctx* c) {
+  if (!c) return ARCHE_EINVAL;
+  if (c->prof) {
+    for (int k = 0; k < PROF_KINDS; ++k) {
+      c->prof->total_ms[k] = 0.0;
+      c->prof->launches[k] = 0;
+    }
+  }
   return ARCHE_OK;
 }
 

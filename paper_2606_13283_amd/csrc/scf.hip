@@ -6,41 +6,15 @@
 #include <mutex>
 
 #include "arche_internal.h"
+#include "profile.h"
 
 namespace {
 
 constexpr double PI = 3.14159265358979323846;
 
 // ---------------------------------------------------------------------------
-// partial-sum helpers
-__device__ inline double reduce_slot_sum(const double* part, int slot, unsigned nb, double* sh) {
-  double v = 0.0;
-  const double* p = part + (size_t)slot * nb;
-  for (unsigned t = threadIdx.x; t < nb; t += blockDim.x) v += coherent_load(p + t);
-  v = block_sum(v, sh);
-  __shared__ double bc;
-  if (threadIdx.x == 0) bc = v;
-  __syncthreads();
-  double r = bc;
-  __syncthreads();
-  return r;
-}
-
-__device__ inline double reduce_slot_max(const double* part, int slot, unsigned nb, double* sh) {
-  double v = -INFINITY;
-  const double* p = part + (size_t)slot * nb;
-  for (unsigned t = threadIdx.x; t < nb; t += blockDim.x) v = fmax(v, coherent_load(p + t));
-  v = block_max(v, sh);
-  __shared__ double bc;
-  if (threadIdx.x == 0) bc = v;
-  __syncthreads();
-  double r = bc;
-  __syncthreads();
-  return r;
-}
-
 __device__ inline void put_slot(double* part, int slot, unsigned nb, double v) {
-  if (threadIdx.x == 0) coherent_store(part + (size_t)slot * nb + blockIdx.x, v);
+  if (threadIdx.x == 0) coherent_store(part + (size_t)slot * nb + blockIdx.x, v);  // read by grid_allreduce
 }
 
 struct ActiveArgs {
@@ -52,7 +26,8 @@ struct ActiveArgs {
   double* n_a;
   ScfState* st;
   double* part;
-  unsigned* bar;
+  double* res;
+  unsigned* flags;  // [nb] arrival flags, then the go word
   int* err;
   const FdTables* fdt;
   int64_t ng;
@@ -64,51 +39,70 @@ struct ActiveArgs {
   int max_newton;
 };
 
+// points per thread kept in registers across the phases of k_scf_active
+constexpr int PPT = 16;
+
 // One cooperative launch per SCF iteration: steps 1-4 of the iteration.
 //  1. V_i = V^ie + V_H[n_i] + v_xc(n_i) + v_vW[n_i]
 //  2. Newton search of mu with N(mu) = int c_n I_{1/2}((mu - V_i)/kT) = N_e
 //     (eq. newtonmu), safeguarded by bisection in [min V_i, max V_i] + kT eta_0
 //  3. n_a, dn = n_i - n_a, and the reductions K, ||dn||, ||n_a||, U_xc, max|dn|/n_a
 //  4. convergence test and the More switch
-// Every block reduces the per-block partials of all blocks in the same order,
-// so every block holds bit-identical scalars and takes the same branches.
+// Global sums go through grid_allreduce, which hands every block the same
+// fixed-order result, so every block takes the same branches.  With CACHE, the
+// grid fits in PPT points per thread and V_i (and v_xc(n_i)) stay in registers
+// between the phases instead of being re-read.
+template <bool CACHE>
 __global__ void __launch_bounds__(ARCHE_BLOCK) k_scf_active(ActiveArgs a) {
   __shared__ double sh[ARCHE_BLOCK / 64];
+  __shared__ double r[8];
+  __shared__ FdLds fdl;
   ScfState* st = a.st;
   if (st->done) return;
+  fd_lds_load(&fdl, a.fdt);
   const unsigned nb = gridDim.x;
+  unsigned* go = a.flags + nb;
+  // epochs grow by one per all-reduce; each launch owns a disjoint range
+  unsigned epoch = (unsigned)(st->iter + 1) * 256u;
   const int64_t stride = (int64_t)nb * blockDim.x;
   const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double vreg[CACHE ? PPT : 1], xreg[CACHE ? PPT : 1];
 
   // 1. potential assembly
   double vmin = INFINITY, vmax = -INFINITY, vsum = 0.0;
-  for (int64_t i = i0; i < a.ng; i += stride) {
-    double n = a.n_i[i];
-    double v = a.Vie[i] + a.VH[i];
-    if (a.xc) {
-      double vxc;
-      lda_xc(n, vxc);
-      v += vxc;
+  {
+    int q = 0;
+    for (int64_t i = i0; i < a.ng; i += stride, ++q) {
+      const double n = a.n_i[i];
+      double v = a.Vie[i] + a.VH[i];
+      double vxc = 0.0;
+      if (a.xc) {
+        lda_xc(n, vxc);
+        v += vxc;
+      }
+      if (a.lam != 0.0) v += -0.5 * a.lam * a.lap_i[i] / sqrt(n);
+      if (CACHE) {
+        vreg[q] = v;
+        xreg[q] = vxc;
+      }
+      a.Vi[i] = v;
+      vmin = fmin(vmin, v);
+      vmax = fmax(vmax, v);
+      vsum += v;
     }
-    if (a.lam != 0.0) v += -0.5 * a.lam * a.lap_i[i] / sqrt(n);
-    a.Vi[i] = v;
-    vmin = fmin(vmin, v);
-    vmax = fmax(vmax, v);
-    vsum += v;
   }
   {
-    double s = block_sum(vsum, sh);
-    put_slot(a.part, 0, nb, s);
-    double m = block_max(vmax, sh);
-    put_slot(a.part, 1, nb, m);
-    double q = block_max(-vmin, sh);
-    put_slot(a.part, 2, nb, q);
+    double v = block_sum(vsum, sh);
+    put_slot(a.part, 0, nb, v);
+    v = block_max(vmax, sh);
+    put_slot(a.part, 1, nb, v);
+    v = block_max(-vmin, sh);
+    put_slot(a.part, 2, nb, v);
   }
-  grid_barrier(a.bar, a.bar + 1, nb, a.err);
-  const double Vsum = reduce_slot_sum(a.part, 0, nb, sh);
-  const double Vmax = reduce_slot_max(a.part, 1, nb, sh);
-  const double Vmin = -reduce_slot_max(a.part, 2, nb, sh);
+  grid_allreduce(a.part, a.res, 0, 3, 0x6u, nb, a.flags, go, ++epoch, a.err, r, sh);
+  const double Vsum = r[0], Vmax = r[1], Vmin = -r[2];
   const double kT = a.kT;
+  const double ikT = 1.0 / kT;
   double lo = Vmin + kT * a.eta0;
   double hi = Vmax + kT * a.eta0;
   double mu = st->mu;
@@ -120,20 +114,23 @@ __global__ void __launch_bounds__(ARCHE_BLOCK) k_scf_active(ActiveArgs a) {
   double N = 0.0, dN = 0.0;
   for (it = 1; it <= a.max_newton; ++it) {
     double s12 = 0.0, sm12 = 0.0;
-    for (int64_t i = i0; i < a.ng; i += stride) {
-      double im, ip;
-      fd_m12_p12(a.fdt, (mu - a.Vi[i]) / kT, im, ip);
-      s12 += ip;
-      sm12 += im;
+    {
+      int q = 0;
+      for (int64_t i = i0; i < a.ng; i += stride, ++q) {
+        double im, ip;
+        const double v = CACHE ? vreg[q] : a.Vi[i];
+        fd_m12_p12_lds(fdl, (mu - v) * ikT, im, ip);
+        s12 += ip;
+        sm12 += im;
+      }
     }
-    const int slot = 3 + 2 * (it & 1);
-    double b12 = block_sum(s12, sh);
-    put_slot(a.part, slot, nb, b12);
-    double bm12 = block_sum(sm12, sh);
-    put_slot(a.part, slot + 1, nb, bm12);
-    grid_barrier(a.bar, a.bar + 1, nb, a.err);
-    N = a.dv * a.cn * reduce_slot_sum(a.part, slot, nb, sh);
-    dN = a.dv * a.cn / (2.0 * kT) * reduce_slot_sum(a.part, slot + 1, nb, sh);
+    double b = block_sum(s12, sh);
+    put_slot(a.part, 3, nb, b);
+    b = block_sum(sm12, sh);
+    put_slot(a.part, 4, nb, b);
+    grid_allreduce(a.part, a.res, 3, 2, 0u, nb, a.flags, go, ++epoch, a.err, r, sh);
+    N = a.dv * a.cn * r[0];
+    dN = a.dv * a.cn * 0.5 * ikT * r[1];
     const double f = N - a.Ne;
     if (fabs(f) <= 1e-14 * a.Ne) {
       found = true;
@@ -156,49 +153,51 @@ __global__ void __launch_bounds__(ARCHE_BLOCK) k_scf_active(ActiveArgs a) {
 
   // 3. active density and the mixing reductions
   double sdd = 0.0, snn = 0.0, sK = 0.0, sU = 0.0, sNa = 0.0, smax = 0.0;
-  const double cchi = a.cn / (2.0 * kT);
-  for (int64_t i = i0; i < a.ng; i += stride) {
-    double im, ip;
-    fd_m12_p12(a.fdt, (mu - a.Vi[i]) / kT, im, ip);
-    const double na = a.cn * ip;
-    const double chi = cchi * im;
-    const double ni = a.n_i[i];
-    const double d = ni - na;
-    a.n_a[i] = na;
-    sdd += d * d;
-    snn += na * na;
-    sK += d * d / chi;
-    sNa += na;
-    if (a.xc) {
-      double vi, va;
-      lda_xc(ni, vi);
-      lda_xc(na, va);
-      sU += (vi - va) * d;
+  const double cchi = a.cn * 0.5 * ikT;
+  {
+    int q = 0;
+    for (int64_t i = i0; i < a.ng; i += stride, ++q) {
+      double im, ip;
+      const double v = CACHE ? vreg[q] : a.Vi[i];
+      fd_m12_p12_lds(fdl, (mu - v) * ikT, im, ip);
+      const double na = a.cn * ip;
+      const double chi = cchi * im;
+      const double ni = a.n_i[i];
+      const double d = ni - na;
+      a.n_a[i] = na;
+      sdd += d * d;
+      snn += na * na;
+      sK += d * d / chi;
+      sNa += na;
+      if (a.xc) {
+        double vi, va;
+        if (CACHE)
+          vi = xreg[q];
+        else
+          lda_xc(ni, vi);
+        lda_xc(na, va);
+        sU += (vi - va) * d;
+      }
+      smax = fmax(smax, fabs(d) / na);
     }
-    smax = fmax(smax, fabs(d) / na);
   }
   {
     double v;
     v = block_sum(sdd, sh);
-    put_slot(a.part, 7, nb, v);
+    put_slot(a.part, 5, nb, v);
     v = block_sum(snn, sh);
-    put_slot(a.part, 8, nb, v);
+    put_slot(a.part, 6, nb, v);
     v = block_sum(sK, sh);
-    put_slot(a.part, 9, nb, v);
+    put_slot(a.part, 7, nb, v);
     v = block_sum(sU, sh);
-    put_slot(a.part, 10, nb, v);
+    put_slot(a.part, 8, nb, v);
     v = block_sum(sNa, sh);
-    put_slot(a.part, 11, nb, v);
+    put_slot(a.part, 9, nb, v);
     v = block_max(smax, sh);
-    put_slot(a.part, 12, nb, v);
+    put_slot(a.part, 10, nb, v);
   }
-  grid_barrier(a.bar, a.bar + 1, nb, a.err);
-  const double DD = reduce_slot_sum(a.part, 7, nb, sh);
-  const double NN = reduce_slot_sum(a.part, 8, nb, sh);
-  const double KK = reduce_slot_sum(a.part, 9, nb, sh);
-  const double UU = reduce_slot_sum(a.part, 10, nb, sh);
-  const double NA = reduce_slot_sum(a.part, 11, nb, sh);
-  const double MX = reduce_slot_max(a.part, 12, nb, sh);
+  grid_allreduce(a.part, a.res, 5, 6, 0x20u, nb, a.flags, go, ++epoch, a.err, r, sh);
+  const double DD = r[0], NN = r[1], KK = r[2], UU = r[3], NA = r[4], MX = r[5];
 
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     const double res = sqrt(DD / NN);
@@ -420,13 +419,14 @@ __global__ void __launch_bounds__(ARCHE_BLOCK) k_fill(double* x, int64_t n, doub
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) x[i] = v;
 }
 
-__global__ void k_state_init(ScfState* st, unsigned* bar, int* err, double mu0) {
-  ScfState z{};
-  z.mu = mu0;
-  *st = z;
-  bar[0] = 0;
-  bar[1] = 0;
-  *err = 0;
+__global__ void k_state_init(ScfState* st, unsigned* flags, int nflags, int* err, double mu0) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ScfState z{};
+    z.mu = mu0;
+    *st = z;
+    *err = 0;
+  }
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nflags; i += gridDim.x * blockDim.x) flags[i] = 0u;
 }
 
 unsigned grid_for(int64_t n) {
@@ -479,7 +479,8 @@ const FdTables* fd_tables_device(int device) {
 }
 
 hipError_t scf_reset_state(arche_ctx* c, double mu0) {
-  hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, c->stream, c->state, c->bar, c->err_d, mu0);
+  hipLaunchKernelGGL(k_state_init, dim3(4), dim3(ARCHE_BLOCK), 0, c->stream, c->state, c->bar, c->coop_blocks + 1,
+                     c->err_d, mu0);
   return hipGetLastError();
 }
 
@@ -524,8 +525,11 @@ int scf_coop_blocks(int64_t ng) {
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_scf_active, ARCHE_BLOCK, 0) != hipSuccess) return 0;
+  int per_cu = 0, per_cu2 = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_scf_active<true>, ARCHE_BLOCK, 0) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu2, k_scf_active<false>, ARCHE_BLOCK, 0) != hipSuccess)
+    return 0;
+  per_cu = std::min(per_cu, per_cu2);
   int64_t b = std::min<int64_t>((int64_t)per_cu * cus, 2 * (int64_t)cus);
   b = std::min<int64_t>(b, (ng + 4 * ARCHE_BLOCK - 1) / (4 * ARCHE_BLOCK));
   return (int)std::max<int64_t>(b, 1);
@@ -543,7 +547,8 @@ hipError_t scf_iteration(arche_ctx* c) {
   a.n_a = c->n_a;
   a.st = c->state;
   a.part = c->partials;
-  a.bar = c->bar;
+  a.res = c->sums + 32;
+  a.flags = c->bar;
   a.err = c->err_d;
   a.fdt = c->fdt;
   a.ng = g.ng;
@@ -558,10 +563,14 @@ hipError_t scf_iteration(arche_ctx* c) {
   a.mixing = p.mixing;
   a.warmup = p.more_warmup;
   a.trust = p.more_trust;
-  a.max_newton = 200;
+  a.max_newton = 200;  // < 250 all-reduces per launch keeps the epochs of launches disjoint
   void* args[] = {&a};
-  HIP_TRY(hipLaunchCooperativeKernel((const void*)k_scf_active, dim3(c->coop_blocks), dim3(ARCHE_BLOCK), args, 0,
-                                     c->stream));
+  const bool cache = g.ng <= (int64_t)PPT * c->coop_blocks * ARCHE_BLOCK;
+  {
+    ProfScope prof(PROF_SCF_ACTIVE, c->stream);
+    HIP_TRY(hipLaunchCooperativeKernel(cache ? (const void*)k_scf_active<true> : (const void*)k_scf_active<false>,
+                                       dim3(c->coop_blocks), dim3(ARCHE_BLOCK), args, 0, c->stream));
+  }
   // n^_a
   HIP_TRY(fft_r2c(&c->plan, c->n_a, c->nhat_a, 1.0, g.dv, c->stream));
   const bool vw = p.lambda_vw != 0.0;
