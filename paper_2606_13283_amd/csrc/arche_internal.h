@@ -119,6 +119,7 @@ hipError_t scf_initial_uniform(arche_ctx* c);
 hipError_t scf_initial_one_center(arche_ctx* c, int* used_fallback);  // ionic.hip
 hipError_t scf_prepare_input(arche_ctx* c);  // n^_i, V_H, lap sqrt(n_i) from n_i
 int scf_coop_blocks(int64_t ng);
+size_t scf_part_offset(const arche_ctx* c);  // start of the non-cooperative partials
 
 // ionic (ionic.hip)
 hipError_t ionic_structure(arche_ctx* c);  // phases, S+/S-, SZ, V^ie

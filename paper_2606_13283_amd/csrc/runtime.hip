@@ -358,7 +358,7 @@ arche_status arche_scf_init(const arche_params* p, void* hip_stream, arche_ctx**
   ok = ok && dalloc(&c->spec_d, (size_t)n) == hipSuccess;
   ok = ok && dalloc(&c->sp_order, (size_t)n) == hipSuccess;
   ok = ok && dalloc(&c->sp_begin, (size_t)ns + 1) == hipSuccess;
-  c->partial_cap = 16 * c->coop_blocks + 8 * 1024 + n + 64;
+  c->partial_cap = (int)scf_part_offset(c) + 16 * 1024 + n + 64;
   ok = ok && dalloc(&c->partials, (size_t)c->partial_cap) == hipSuccess;
   ok = ok && dalloc(&c->sums, 64) == hipSuccess;
   ok = ok && dalloc(&c->state, 1) == hipSuccess;

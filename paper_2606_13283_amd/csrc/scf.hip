@@ -25,12 +25,12 @@ struct ActiveArgs {
   double* Vi;
   double* n_a;
   ScfState* st;
-  double* part;
-  double* res;
-  unsigned* flags;  // [nb] arrival flags, then the go word
+  double* part;     // [13][nchunk] chunk partials
+  double* res;      // reduced scalars
+  unsigned* flags;  // [G] arrival flags of the group, then the go word
   int* err;
   const FdTables* fdt;
-  int64_t ng;
+  int64_t ng, nchunk;
   double dv, kT, cn, Ne, lam;
   int xc;
   double eta0, tol;
@@ -39,67 +39,69 @@ struct ActiveArgs {
   int max_newton;
 };
 
-// points per thread kept in registers across the phases of k_scf_active
+// The grid is cut into chunks of SCF_CHUNK consecutive points; thread t of the
+// block that owns a chunk handles points t + ARCHE_BLOCK*q, q < PPT.  Every
+// global sum is a sum of per-chunk partials in chunk order, so the result does
+// not depend on how many blocks share the work (a batched solve, with fewer
+// blocks per snapshot, is bit-identical to an unbatched one).
 constexpr int PPT = 16;
+constexpr int SCF_CHUNK = ARCHE_BLOCK * PPT;
 
-// One cooperative launch per SCF iteration: steps 1-4 of the iteration.
+__device__ inline void put_chunk(double* part, int slot, int64_t nchunk, int64_t c, double v) {
+  if (threadIdx.x == 0) coherent_store(part + (int64_t)slot * nchunk + c, v);  // read by grid_allreduce
+}
+
+// Steps 1-4 of one SCF iteration for one system, run by a group of G
+// co-resident blocks (lb = this block's index in the group):
 //  1. V_i = V^ie + V_H[n_i] + v_xc(n_i) + v_vW[n_i]
 //  2. Newton search of mu with N(mu) = int c_n I_{1/2}((mu - V_i)/kT) = N_e
 //     (eq. newtonmu), safeguarded by bisection in [min V_i, max V_i] + kT eta_0
 //  3. n_a, dn = n_i - n_a, and the reductions K, ||dn||, ||n_a||, U_xc, max|dn|/n_a
 //  4. convergence test and the More switch
-// Global sums go through grid_allreduce, which hands every block the same
-// fixed-order result, so every block takes the same branches.  With CACHE, the
-// grid fits in PPT points per thread and V_i (and v_xc(n_i)) stay in registers
-// between the phases instead of being re-read.
+// grid_allreduce hands every block of the group the same fixed-order result, so
+// all of them take the same branches.  With CACHE (at most one chunk per block)
+// V_i and v_xc(n_i) stay in registers between the phases.
 template <bool CACHE>
-__global__ void __launch_bounds__(ARCHE_BLOCK) k_scf_active(ActiveArgs a) {
-  __shared__ double sh[ARCHE_BLOCK / 64];
-  __shared__ double r[8];
-  __shared__ FdLds fdl;
+__device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigned G, const FdLds& fdl, double* sh,
+                                       double* r) {
   ScfState* st = a.st;
-  if (st->done) return;
-  fd_lds_load(&fdl, a.fdt);
-  const unsigned nb = gridDim.x;
-  unsigned* go = a.flags + nb;
-  // epochs grow by one per all-reduce; each launch owns a disjoint range
-  unsigned epoch = (unsigned)(st->iter + 1) * 256u;
-  const int64_t stride = (int64_t)nb * blockDim.x;
-  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double vreg[CACHE ? PPT : 1], xreg[CACHE ? PPT : 1];
+  unsigned* go = a.flags + G;
+  unsigned epoch = (unsigned)(st->iter + 1) * 256u;  // grows by one per all-reduce; disjoint per launch
+  const int64_t nchunk = a.nchunk;
+  double vreg[CACHE ? PPT : 1];
+  // with CACHE each block owns at most one chunk (lb), otherwise chunks lb, lb+G, ...
+#define FOR_CHUNKS(c)                                           \
+  for (int64_t c = lb; c < nchunk; c += (CACHE ? nchunk : G))
 
   // 1. potential assembly
-  double vmin = INFINITY, vmax = -INFINITY, vsum = 0.0;
-  {
-    int q = 0;
-    for (int64_t i = i0; i < a.ng; i += stride, ++q) {
-      const double n = a.n_i[i];
-      double v = a.Vie[i] + a.VH[i];
-      double vxc = 0.0;
-      if (a.xc) {
-        lda_xc(n, vxc);
-        v += vxc;
+  FOR_CHUNKS(c) {
+    double vmin = INFINITY, vmax = -INFINITY, vsum = 0.0;
+    for (int q = 0; q < PPT; ++q) {
+      const int64_t i = c * SCF_CHUNK + threadIdx.x + (int64_t)ARCHE_BLOCK * q;
+      if (i < a.ng) {
+        const double n = a.n_i[i];
+        double v = a.Vie[i] + a.VH[i];
+        if (a.xc) {
+          double vxc;
+          lda_xc(n, vxc);
+          v += vxc;
+        }
+        if (a.lam != 0.0) v += -0.5 * a.lam * a.lap_i[i] / sqrt(n);
+        if (CACHE) vreg[q] = v;
+        a.Vi[i] = v;
+        vmin = fmin(vmin, v);
+        vmax = fmax(vmax, v);
+        vsum += v;
       }
-      if (a.lam != 0.0) v += -0.5 * a.lam * a.lap_i[i] / sqrt(n);
-      if (CACHE) {
-        vreg[q] = v;
-        xreg[q] = vxc;
-      }
-      a.Vi[i] = v;
-      vmin = fmin(vmin, v);
-      vmax = fmax(vmax, v);
-      vsum += v;
     }
-  }
-  {
     double v = block_sum(vsum, sh);
-    put_slot(a.part, 0, nb, v);
+    put_chunk(a.part, 0, nchunk, c, v);
     v = block_max(vmax, sh);
-    put_slot(a.part, 1, nb, v);
+    put_chunk(a.part, 1, nchunk, c, v);
     v = block_max(-vmin, sh);
-    put_slot(a.part, 2, nb, v);
+    put_chunk(a.part, 2, nchunk, c, v);
   }
-  grid_allreduce(a.part, a.res, 0, 3, 0x6u, nb, a.flags, go, ++epoch, a.err, r, sh);
+  grid_allreduce(a.part, nchunk, a.res, 0, 3, 0x6u, G, lb, a.flags, go, ++epoch, a.err, r, sh);
   const double Vsum = r[0], Vmax = r[1], Vmin = -r[2];
   const double kT = a.kT;
   const double ikT = 1.0 / kT;
@@ -113,22 +115,24 @@ __global__ void __launch_bounds__(ARCHE_BLOCK) k_scf_active(ActiveArgs a) {
   bool found = false;
   double N = 0.0, dN = 0.0;
   for (it = 1; it <= a.max_newton; ++it) {
-    double s12 = 0.0, sm12 = 0.0;
-    {
-      int q = 0;
-      for (int64_t i = i0; i < a.ng; i += stride, ++q) {
-        double im, ip;
-        const double v = CACHE ? vreg[q] : a.Vi[i];
-        fd_m12_p12_lds(fdl, (mu - v) * ikT, im, ip);
-        s12 += ip;
-        sm12 += im;
+    FOR_CHUNKS(c) {
+      double s12 = 0.0, sm12 = 0.0;
+      for (int q = 0; q < PPT; ++q) {
+        const int64_t i = c * SCF_CHUNK + threadIdx.x + (int64_t)ARCHE_BLOCK * q;
+        if (i < a.ng) {
+          double im, ip;
+          const double v = CACHE ? vreg[q] : a.Vi[i];
+          fd_m12_p12_lds(fdl, (mu - v) * ikT, im, ip);
+          s12 += ip;
+          sm12 += im;
+        }
       }
+      double b = block_sum(s12, sh);
+      put_chunk(a.part, 3, nchunk, c, b);
+      b = block_sum(sm12, sh);
+      put_chunk(a.part, 4, nchunk, c, b);
     }
-    double b = block_sum(s12, sh);
-    put_slot(a.part, 3, nb, b);
-    b = block_sum(sm12, sh);
-    put_slot(a.part, 4, nb, b);
-    grid_allreduce(a.part, a.res, 3, 2, 0u, nb, a.flags, go, ++epoch, a.err, r, sh);
+    grid_allreduce(a.part, nchunk, a.res, 3, 2, 0u, G, lb, a.flags, go, ++epoch, a.err, r, sh);
     N = a.dv * a.cn * r[0];
     dN = a.dv * a.cn * 0.5 * ikT * r[1];
     const double f = N - a.Ne;
@@ -152,54 +156,52 @@ __global__ void __launch_bounds__(ARCHE_BLOCK) k_scf_active(ActiveArgs a) {
   if (it > a.max_newton) it = a.max_newton;
 
   // 3. active density and the mixing reductions
-  double sdd = 0.0, snn = 0.0, sK = 0.0, sU = 0.0, sNa = 0.0, smax = 0.0;
   const double cchi = a.cn * 0.5 * ikT;
-  {
-    int q = 0;
-    for (int64_t i = i0; i < a.ng; i += stride, ++q) {
-      double im, ip;
-      const double v = CACHE ? vreg[q] : a.Vi[i];
-      fd_m12_p12_lds(fdl, (mu - v) * ikT, im, ip);
-      const double na = a.cn * ip;
-      const double chi = cchi * im;
-      const double ni = a.n_i[i];
-      const double d = ni - na;
-      a.n_a[i] = na;
-      sdd += d * d;
-      snn += na * na;
-      sK += d * d / chi;
-      sNa += na;
-      if (a.xc) {
-        double vi, va;
-        if (CACHE)
-          vi = xreg[q];
-        else
+  FOR_CHUNKS(c) {
+    double sdd = 0.0, snn = 0.0, sK = 0.0, sU = 0.0, sNa = 0.0, smax = 0.0;
+    for (int q = 0; q < PPT; ++q) {
+      const int64_t i = c * SCF_CHUNK + threadIdx.x + (int64_t)ARCHE_BLOCK * q;
+      if (i < a.ng) {
+        double im, ip;
+        const double v = CACHE ? vreg[q] : a.Vi[i];
+        fd_m12_p12_lds(fdl, (mu - v) * ikT, im, ip);
+        const double na = a.cn * ip;
+        const double chi = cchi * im;
+        const double ni = a.n_i[i];
+        const double d = ni - na;
+        a.n_a[i] = na;
+        sdd += d * d;
+        snn += na * na;
+        sK += d * d / chi;
+        sNa += na;
+        if (a.xc) {
+          double vi, va;
           lda_xc(ni, vi);
-        lda_xc(na, va);
-        sU += (vi - va) * d;
+          lda_xc(na, va);
+          sU += (vi - va) * d;
+        }
+        smax = fmax(smax, fabs(d) / na);
       }
-      smax = fmax(smax, fabs(d) / na);
     }
-  }
-  {
     double v;
     v = block_sum(sdd, sh);
-    put_slot(a.part, 5, nb, v);
+    put_chunk(a.part, 5, nchunk, c, v);
     v = block_sum(snn, sh);
-    put_slot(a.part, 6, nb, v);
+    put_chunk(a.part, 6, nchunk, c, v);
     v = block_sum(sK, sh);
-    put_slot(a.part, 7, nb, v);
+    put_chunk(a.part, 7, nchunk, c, v);
     v = block_sum(sU, sh);
-    put_slot(a.part, 8, nb, v);
+    put_chunk(a.part, 8, nchunk, c, v);
     v = block_sum(sNa, sh);
-    put_slot(a.part, 9, nb, v);
+    put_chunk(a.part, 9, nchunk, c, v);
     v = block_max(smax, sh);
-    put_slot(a.part, 10, nb, v);
+    put_chunk(a.part, 10, nchunk, c, v);
   }
-  grid_allreduce(a.part, a.res, 5, 6, 0x20u, nb, a.flags, go, ++epoch, a.err, r, sh);
+#undef FOR_CHUNKS
+  grid_allreduce(a.part, nchunk, a.res, 5, 6, 0x20u, G, lb, a.flags, go, ++epoch, a.err, r, sh);
   const double DD = r[0], NN = r[1], KK = r[2], UU = r[3], NA = r[4], MX = r[5];
 
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (lb == 0 && threadIdx.x == 0) {
     const double res = sqrt(DD / NN);
     const int t = st->iter;
     int more = st->more_on;
@@ -221,6 +223,39 @@ __global__ void __launch_bounds__(ARCHE_BLOCK) k_scf_active(ActiveArgs a) {
     if (bad) st->err = 1;
     st->done = (res < a.tol) || bad;
   }
+}
+
+// One system: the whole cooperative grid is the group.
+template <bool CACHE>
+__global__ void __launch_bounds__(ARCHE_BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) k_scf_active(ActiveArgs a) {
+  __shared__ double sh[ARCHE_BLOCK / 64];
+  __shared__ double r[8];
+  __shared__ FdLds fdl;
+  if (a.st->done) return;
+  fd_lds_load(&fdl, a.fdt);
+  __syncthreads();
+  scf_active_body<CACHE>(a, blockIdx.x, gridDim.x, fdl, sh, r);
+}
+
+// Many systems in one cooperative launch: system s owns blocks
+// [group_begin[s], group_begin[s+1]) (its group), converged systems drop out.
+__global__ void __launch_bounds__(ARCHE_BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_scf_active_batch(const ActiveArgs* __restrict__ args, const int* __restrict__ group_begin, int nsys) {
+  __shared__ double sh[ARCHE_BLOCK / 64];
+  __shared__ double r[8];
+  __shared__ FdLds fdl;
+  int s = 0;
+  while (s + 1 < nsys && group_begin[s + 1] <= (int)blockIdx.x) ++s;
+  const ActiveArgs a = args[s];
+  if (a.st->done) return;
+  fd_lds_load(&fdl, a.fdt);
+  __syncthreads();
+  const unsigned lb = blockIdx.x - group_begin[s];
+  const unsigned G = group_begin[s + 1] - group_begin[s];
+  if ((int64_t)G >= a.nchunk)
+    scf_active_body<true>(a, lb, G, fdl, sh, r);
+  else
+    scf_active_body<false>(a, lb, G, fdl, sh, r);
 }
 
 // U_vW = int (v_vW[n_i] - v_vW[n_a]) (n_i - n_a), v_vW[n] = -(lambda/2) lap(sqrt n)/sqrt n
@@ -444,6 +479,11 @@ unsigned grid_for(int64_t n) {
 
 }  // namespace
 
+size_t scf_part_offset(const arche_ctx* c) {
+  const int64_t nchunk = (c->g.ng + SCF_CHUNK - 1) / SCF_CHUNK;
+  return 16 * (size_t)std::max<int64_t>(nchunk, c->coop_blocks);
+}
+
 int red_blocks(int64_t n) {
   int64_t b = (n + 4 * ARCHE_BLOCK - 1) / (4 * ARCHE_BLOCK);
   if (b > 1024) b = 1024;
@@ -535,6 +575,48 @@ int scf_coop_blocks(int64_t ng) {
   return (int)std::max<int64_t>(b, 1);
 }
 
+// The rest of an SCF iteration with the spectral and pointwise steps fused into
+// the FFT passes (fft.h): R2C(n_a) also sums U_H; [More + vW: R2C(sqrt n_a) with
+// the Laplacian on store, C2R that sums U_vW instead of storing]; the weight;
+// C2R of n_o^/(pi k^2) that forms n_o^ from n^_a and n^_i on load; R2C of
+// sqrt(n_o) that forms n_o on load, Laplacian on store, C2R -> lap sqrt(n_o).
+static hipError_t scf_iteration_rest_fused(arche_ctx* c, bool vw, bool more) {
+  const GridInfo& g = c->g;
+  const arche_params& p = c->p;
+  const int nbh = fft_x_blocks(&c->plan);
+  const int nbv = fft_z_blocks(&c->plan);
+  double* part_h = c->partials + scf_part_offset(c);
+  double* part_v = part_h + nbh;
+  FftFuse f{};
+  f.w = &c->state->w;
+  f.n_i = c->n_i;
+  f.n_a = c->n_a;
+  f.lap_i = c->lap_i;
+  f.nhat_i = c->nhat_i;
+  f.lam = p.lambda_vw;
+  f.L[0] = g.L[0];
+  f.L[1] = g.L[1];
+  f.L[2] = g.L[2];
+  f.partials = part_h;
+  HIP_TRY(fft_r2c_fused(&c->plan, c->n_a, c->nhat_a, 1.0, g.dv, FUSE_NONE, R2C_OUT_UH, f, c->stream));
+  if (more && vw) {
+    HIP_TRY(fft_r2c_fused(&c->plan, c->n_a, c->ctmp, 1.0, g.dv, R2C_IN_SQRT, R2C_OUT_LAP, f, c->stream));
+    f.partials = part_v;
+    HIP_TRY(fft_c2r_fused(&c->plan, c->ctmp, c->ctmp, nullptr, 1.0 / g.vol, FUSE_NONE, C2R_OUT_UVW, f, c->stream));
+  }
+  hipLaunchKernelGGL(k_mix_weight, dim3(1), dim3(ARCHE_BLOCK), 0, c->stream, c->state, part_h, nbh, part_v, nbv,
+                     (int)(more && vw), g.vol, g.dv, p.w_fixed);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(fft_c2r_fused(&c->plan, c->nhat_a, c->ctmp, c->VH, 1.0 / g.vol, C2R_IN_MIX, FUSE_NONE, f, c->stream));
+  if (vw) {
+    HIP_TRY(fft_r2c_fused(&c->plan, c->n_a, c->ctmp, 1.0, g.dv, R2C_IN_MIX_SQRT, R2C_OUT_LAP, f, c->stream));
+    return fft_c2r(&c->plan, c->ctmp, c->lap_i, 1.0 / g.vol, c->stream);
+  }
+  hipLaunchKernelGGL(k_real_mix, dim3(grid_for(g.ng)), dim3(ARCHE_BLOCK), 0, c->stream, (const ScfState*)c->state,
+                     c->n_i, c->n_a, c->rtmp, g.ng);
+  return hipGetLastError();
+}
+
 hipError_t scf_iteration(arche_ctx* c) {
   const GridInfo& g = c->g;
   const arche_params& p = c->p;
@@ -552,6 +634,7 @@ hipError_t scf_iteration(arche_ctx* c) {
   a.err = c->err_d;
   a.fdt = c->fdt;
   a.ng = g.ng;
+  a.nchunk = (g.ng + SCF_CHUNK - 1) / SCF_CHUNK;
   a.dv = g.dv;
   a.kT = p.kT;
   a.cn = std::pow(2.0 * p.kT, 1.5) / (2.0 * PI * PI);
@@ -565,19 +648,20 @@ hipError_t scf_iteration(arche_ctx* c) {
   a.trust = p.more_trust;
   a.max_newton = 200;  // < 250 all-reduces per launch keeps the epochs of launches disjoint
   void* args[] = {&a};
-  const bool cache = g.ng <= (int64_t)PPT * c->coop_blocks * ARCHE_BLOCK;
+  const bool cache = a.nchunk <= c->coop_blocks;
   {
     ProfScope prof(PROF_SCF_ACTIVE, c->stream);
     HIP_TRY(hipLaunchCooperativeKernel(cache ? (const void*)k_scf_active<true> : (const void*)k_scf_active<false>,
                                        dim3(c->coop_blocks), dim3(ARCHE_BLOCK), args, 0, c->stream));
   }
-  // n^_a
-  HIP_TRY(fft_r2c(&c->plan, c->n_a, c->nhat_a, 1.0, g.dv, c->stream));
   const bool vw = p.lambda_vw != 0.0;
   const bool more = p.mixing == ARCHE_MIX_MORE;
+  if (fft_fusable(&c->plan)) return scf_iteration_rest_fused(c, vw, more);
+  // n^_a
+  HIP_TRY(fft_r2c(&c->plan, c->n_a, c->nhat_a, 1.0, g.dv, c->stream));
   const int nbr = red_blocks(g.ng);
   const int nbh = red_blocks(g.nh);
-  double* part_h = c->partials + 16 * (size_t)c->coop_blocks;
+  double* part_h = c->partials + scf_part_offset(c);
   double* part_v = part_h + nbh;
   if (more && vw) {
     // lap(sqrt n_a) for the von Weizsaecker part of U
