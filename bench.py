@@ -89,6 +89,56 @@ def cpu_baseline(w, seconds):
                       "and ionic field setup %.1f s not counted)" % (iters, w.name, dt, setup)}
 
 
+def bench_batch(count):
+    """The batched-solve workload: `count` independent 108-atom snapshots (48^3-72^3
+    grids, 1.5-5.4 g/cm^3, 1-20 eV), one SCF each from the uniform density.  Times
+    the snapshots solved one after another on their own contexts against the same
+    snapshots in one batch (first solve, which includes the autotuner's timing
+    rounds, and a second solve with the tuned schedule), and checks that the
+    batched results are bit-identical to the sequential ones."""
+    import numpy as np
+    import torch
+
+    from paper_2606_13283_amd import arche
+    from paper_2606_13283_amd import workloads as W
+
+    ws = W.batch64(count)
+
+    def opts(w):
+        return arche.Options(w_fixed=w.w_fixed, lambda_vw=w.lam, xc=arche.XC_LDA if w.xc else arche.XC_NONE,
+                             init=arche.INIT_UNIFORM, scf_tol=1e-10)
+
+    ctxs = [arche.Context.from_workload(w, opts(w)) for w in ws]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq = [c.solve(w.pos) for c, w in zip(ctxs, ws)]
+    t_seq = time.perf_counter() - t0
+    for c in ctxs:
+        c.close()
+    print("[bench] batch: %d sequential solves in %.3f s (%d SCF iterations)" % (
+        len(ws), t_seq, sum(r["scf_iters"] for r in seq)), file=sys.stderr, flush=True)
+    b = arche.Batch.from_workloads(ws, opts)
+    t0 = time.perf_counter()
+    r1 = b.solve([w.pos for w in ws])
+    t_b1 = time.perf_counter() - t0
+    info1 = b.info()
+    t0 = time.perf_counter()
+    r2 = b.solve([w.pos for w in ws])
+    t_b2 = time.perf_counter() - t0
+    info2 = b.info()
+    b.close()
+    print("[bench] batch: batched %.3f s (tuning solve %.3f s)" % (t_b2, t_b1), file=sys.stderr, flush=True)
+    same = all(x["F"] == y["F"] and x["P"] == y["P"] and x["scf_iters"] == y["scf_iters"]
+               for x, y in zip(seq, r2))
+    iters = sum(r["scf_iters"] for r in seq)
+    grids = sorted({w.grid[0] for w in ws})
+    return {"workload": "batch%d_108Al" % len(ws), "snapshots": len(ws), "grids": grids,
+            "scf_iters_total": iters, "sequential_s": t_seq, "batched_s": t_b2, "batched_first_s": t_b1,
+            "speedup": t_seq / t_b2, "snapshots_per_s": len(ws) / t_b2,
+            "scf_iters_per_s_sequential": iters / t_seq, "scf_iters_per_s_batched": iters / t_b2,
+            "bit_identical_to_sequential": bool(same), "schedule": info2, "tuning": info1}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +147,7 @@ def main():
     ap.add_argument("--workload", default="rand1024")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--batch", type=int, default=64, help="snapshots of the batched-solve comparison (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the whole path on a single MI355X "
@@ -185,6 +236,8 @@ def main():
         "kernels": kernels,
         "roofline": roofline,
     }
+    if args.batch > 0:
+        out["batch"] = bench_batch(args.batch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out))

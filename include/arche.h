@@ -158,6 +158,53 @@ const char *arche_last_error(const arche_ctx *ctx);
 
 const char *arche_version(void);
 
+/* ---- Batched solves: many independent snapshots on one GPU ----------------
+ * A batch holds one context per snapshot (each its own cell, grid, atoms,
+ * temperature and SCF options) on one stream.  arche_batch_solve runs the SCF
+ * of every snapshot together: each pass of an iteration is ONE launch over all
+ * unconverged snapshots of any grid size, the iterations are captured in a HIP
+ * graph, and a snapshot drops out when its own convergence test passes.  Per
+ * snapshot the arithmetic is exactly that of arche_scf_solve on the same
+ * context, so results are bit-identical to unbatched solves.  Scheduling
+ * choices (blocks per snapshot in the cooperative kernel, iterations per graph
+ * launch) are made by an autotuner on the first solve; none of them changes a
+ * result bit.  Supported: grids whose three edges are in {16, 20, 24, 30, 32,
+ * 40, 48, 50, 54, 60, 64, 72, 80, 96}. */
+typedef struct arche_batch arche_batch;
+
+/* p: n_snap problem statements (copied).  hip_stream as in arche_scf_init.
+ * EINVAL for invalid parameters or a grid outside the batched set. */
+arche_status arche_batch_init(int32_t n_snap, const arche_params *p, void *hip_stream, arche_batch **out);
+
+/* pos_host[i]: positions [n_atoms_i][3] of snapshot i.  out[i] receives its
+ * result; forces_host (may be NULL) gives per snapshot a caller array
+ * [n_atoms_i][3] for the forces, or NULL entries to skip.  Returns ENOCONV if
+ * any snapshot did not converge (see out[i].converged), else OK. */
+arche_status arche_batch_solve(arche_batch *b, const double *const *pos_host, arche_result *out,
+                               double *const *forces_host);
+
+/* The context of snapshot i (owned by the batch): density, debug and single
+ * solves on it behave as for a context from arche_scf_init. */
+arche_ctx *arche_batch_context(arche_batch *b, int32_t i);
+
+/* Scheduling of the last solve: info[0] = cooperative blocks of the first
+ * iteration, info[1] = iterations per graph launch, info[2] = 1 if whole
+ * iterations (cooperative kernel included) were graph-captured, 0 if only the
+ * passes after it, info[3] = graph launches, info[4] = times the active set was
+ * compacted, info[5] = 1 if the autotuner measured (0: cached or forced). */
+arche_status arche_batch_info(const arche_batch *b, int32_t info[6]);
+
+/* Force the schedule (0 = let the autotuner choose): blocks of the cooperative
+ * kernel and iterations per graph launch.  For tests of result independence. */
+arche_status arche_batch_set_schedule(arche_batch *b, int32_t coop_blocks, int32_t iters_per_graph);
+
+const char *arche_batch_last_error(const arche_batch *b);
+void arche_batch_free(arche_batch *b);
+
+/* One-shot form: init, solve, free. */
+arche_status arche_scf_solve_batch(int32_t n_snap, const arche_params *p, const double *const *pos_host,
+                                   arche_result *out, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

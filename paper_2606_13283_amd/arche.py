@@ -105,6 +105,23 @@ def load(path: str = LIB_PATH):
     L.arche_profile_reset.restype = st
     L.arche_profile_read.argtypes = [vp, ctypes.c_int32, _dp, ctypes.POINTER(ctypes.c_int64)]
     L.arche_profile_read.restype = st
+    L.arche_batch_init.argtypes = [ctypes.c_int32, ctypes.POINTER(Params), vp, ctypes.POINTER(vp)]
+    L.arche_batch_init.restype = st
+    L.arche_batch_solve.argtypes = [vp, ctypes.POINTER(_dp), ctypes.POINTER(Result), ctypes.POINTER(_dp)]
+    L.arche_batch_solve.restype = st
+    L.arche_batch_context.argtypes = [vp, ctypes.c_int32]
+    L.arche_batch_context.restype = vp
+    L.arche_batch_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    L.arche_batch_info.restype = st
+    L.arche_batch_set_schedule.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+    L.arche_batch_set_schedule.restype = st
+    L.arche_batch_last_error.argtypes = [vp]
+    L.arche_batch_last_error.restype = ctypes.c_char_p
+    L.arche_batch_free.argtypes = [vp]
+    L.arche_batch_free.restype = None
+    L.arche_scf_solve_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(Params), ctypes.POINTER(_dp),
+                                        ctypes.POINTER(Result), vp]
+    L.arche_scf_solve_batch.restype = st
     L.arche_k_fft_r2c.argtypes = [_ip, vp, vp, vp]
     L.arche_k_fft_r2c.restype = st
     L.arche_k_fft_c2r.argtypes = [_ip, vp, vp, vp]
@@ -139,44 +156,53 @@ class Options:
     xc: int = XC_LDA
 
 
+def _make_params(cell, grid, species, Z, rc, mass, kT, opts: Options | None = None):
+    """arche_params for one system; returns it with the arrays it points to."""
+    o = opts or Options()
+    species = np.ascontiguousarray(np.asarray(species, dtype=np.int32).reshape(-1))
+    Z, rc, mass = _f64(Z).reshape(-1), _f64(rc).reshape(-1), _f64(mass).reshape(-1)
+    p = Params()
+    p.n_atoms = species.size
+    p.n_species = Z.size
+    p.species = species.ctypes.data_as(_ip)
+    p.Z, p.rc, p.mass = _ptr(Z), _ptr(rc), _ptr(mass)
+    for a in range(3):
+        p.cell[a] = float(cell[a])
+        p.grid[a] = int(grid[a])
+    p.kT = float(kT)
+    p.lambda_vw = float(o.lambda_vw)
+    p.xc = int(o.xc)
+    p.scf_tol = float(o.scf_tol)
+    p.scf_max_iter = int(o.scf_max_iter)
+    p.mixing = int(o.mixing)
+    p.more_warmup = int(o.more_warmup)
+    p.more_trust = float(o.more_trust)
+    p.w_fixed = float(o.w_fixed)
+    p.init = int(o.init)
+    return p, (species, Z, rc, mass)
+
+
 class Context:
     """One system (cell, grid, species, temperature) on the current HIP device."""
 
     def __init__(self, cell, grid, species, Z, rc, mass, kT, opts: Options | None = None, stream=None):
         L = load()
-        o = opts or Options()
-        self._species = np.ascontiguousarray(np.asarray(species, dtype=np.int32).reshape(-1))
-        self._Z = _f64(Z).reshape(-1)
-        self._rc = _f64(rc).reshape(-1)
-        self._mass = _f64(mass).reshape(-1)
-        p = Params()
-        p.n_atoms = self._species.size
-        p.n_species = self._Z.size
-        p.species = self._species.ctypes.data_as(_ip)
-        p.Z, p.rc, p.mass = _ptr(self._Z), _ptr(self._rc), _ptr(self._mass)
-        for a in range(3):
-            p.cell[a] = float(cell[a])
-            p.grid[a] = int(grid[a])
-        p.kT = float(kT)
-        p.lambda_vw = float(o.lambda_vw)
-        p.xc = int(o.xc)
-        p.scf_tol = float(o.scf_tol)
-        p.scf_max_iter = int(o.scf_max_iter)
-        p.mixing = int(o.mixing)
-        p.more_warmup = int(o.more_warmup)
-        p.more_trust = float(o.more_trust)
-        p.w_fixed = float(o.w_fixed)
-        p.init = int(o.init)
-        self.params = p
-        self.n_atoms = p.n_atoms
-        self.grid = tuple(int(g) for g in grid)
-        self.nh = self.grid[0] * self.grid[1] * (self.grid[2] // 2 + 1)
+        p, keep = _make_params(cell, grid, species, Z, rc, mass, kT, opts)
         h = ctypes.c_void_p()
         s = L.arche_scf_init(ctypes.byref(p), ctypes.c_void_p(stream) if stream else None, ctypes.byref(h))
         if s != OK:
             raise ArcheError(s, L.arche_last_error(None).decode())
+        self._setup(L, h, p, keep, owned=True)
+
+    def _setup(self, L, h, p, keep, owned):
+        self._keep = keep
+        self.params = p
+        self.n_atoms = p.n_atoms
+        self.grid = tuple(int(p.grid[a]) for a in range(3))
+        self.nh = self.grid[0] * self.grid[1] * (self.grid[2] // 2 + 1)
         self._h = h
         self._L = L
+        self._owned = owned
 
     @classmethod
     def from_workload(cls, w, opts: Options | None = None, stream=None):
@@ -256,7 +282,83 @@ class Context:
 
     def close(self):
         if getattr(self, "_h", None):
-            self._L.arche_scf_free(self._h)
+            if self._owned:
+                self._L.arche_scf_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent systems solved together (arche_batch_*): one launch per
+    pass over all unconverged snapshots, graph-captured iterations, results
+    bit-identical to Context.solve on the same system."""
+
+    def __init__(self, systems, stream=None):
+        """systems: list of (cell, grid, species, Z, rc, mass, kT, Options)."""
+        L = load()
+        self._L = L
+        made = [_make_params(*sy) for sy in systems]
+        self._keep = [k for _, k in made]
+        self.params = [p for p, _ in made]
+        arr = (Params * len(made))(*self.params)
+        self._arr = arr
+        self.n = len(made)
+        self.n_atoms = [p.n_atoms for p in self.params]
+        h = ctypes.c_void_p()
+        s = L.arche_batch_init(self.n, arr, ctypes.c_void_p(stream) if stream else None, ctypes.byref(h))
+        if s != OK:
+            raise ArcheError(s, "arche_batch_init failed")
+        self._h = h
+
+    @classmethod
+    def from_workloads(cls, ws, opts_of=None, stream=None):
+        opts_of = opts_of or (lambda w: Options(w_fixed=w.w_fixed, lambda_vw=w.lam,
+                                                xc=XC_LDA if w.xc else XC_NONE, init=INIT_UNIFORM))
+        return cls([(w.cell, w.grid, w.species, w.Z, w.rc, w.mass, w.kT, opts_of(w)) for w in ws], stream)
+
+    def _check(self, s, allow=()):
+        if s != OK and s not in allow:
+            raise ArcheError(s, self._L.arche_batch_last_error(self._h).decode())
+        return s
+
+    def solve(self, positions, forces=False, allow_noconv=False):
+        """Returns the result dicts (and the force arrays when forces=True)."""
+        pos = [_f64(p, (n, 3)) for p, n in zip(positions, self.n_atoms)]
+        pp = (_dp * self.n)(*[_ptr(p) for p in pos])
+        res = (Result * self.n)()
+        F = [np.empty((n, 3)) for n in self.n_atoms] if forces else None
+        fp = (_dp * self.n)(*[_ptr(f) for f in F]) if forces else None
+        s = self._L.arche_batch_solve(self._h, pp, res, fp)
+        self._check(s, (ENOCONV,) if allow_noconv else ())
+        out = [r.as_dict() for r in res]
+        return (out, F) if forces else out
+
+    def context(self, i):
+        """Non-owning Context for snapshot i (density, debug, single solves)."""
+        h = self._L.arche_batch_context(self._h, int(i))
+        if not h:
+            raise IndexError(i)
+        c = Context.__new__(Context)
+        c._setup(self._L, ctypes.c_void_p(h), self.params[i], self._keep[i], owned=False)
+        return c
+
+    def info(self):
+        a = (ctypes.c_int32 * 6)()
+        self._check(self._L.arche_batch_info(self._h, a))
+        return {"coop_blocks": a[0], "iters_per_graph": a[1], "graph_whole_iteration": bool(a[2]),
+                "graph_launches": a[3], "compactions": a[4], "tuned_now": bool(a[5])}
+
+    def set_schedule(self, coop_blocks=0, iters_per_graph=0):
+        self._check(self._L.arche_batch_set_schedule(self._h, int(coop_blocks), int(iters_per_graph)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.arche_batch_free(self._h)
             self._h = None
 
     def __del__(self):

@@ -11,13 +11,16 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libarche.so")
-SOURCES = ["fft.hip", "scf.hip", "ionic.hip", "runtime.hip", "kernels_abi.hip"]
+SOURCES = ["fft.hip", "fft_batch.hip", "scf.hip", "batch.hip", "ionic.hip", "runtime.hip", "kernels_abi.hip"]
 ARCH = os.environ.get("ARCHE_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=" + ARCH,
     # keep the compiler from emitting packed-FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-add fusion decided per source expression, so the same tile code
+    # rounds the same way in every kernel it is inlined into
+    "-ffp-contract=on",
     "-fno-gpu-rdc", "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
 

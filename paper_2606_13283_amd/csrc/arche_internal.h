@@ -48,6 +48,71 @@ struct SpeciesInfo {
   double rc[ARCHE_MAX_SPECIES];
 };
 
+// Arguments of the cooperative SCF kernel for one system (scf.hip): steps 1-4
+// of an iteration (potential, chemical potential, active density, sums).
+struct ActiveArgs {
+  const double* Vie;
+  const double* VH;
+  const double* lap_i;
+  const double* n_i;
+  double* Vi;
+  double* n_a;
+  ScfState* st;
+  double* part;     // [13][nchunk] chunk partials
+  double* res;      // reduced scalars
+  unsigned* flags;  // [G] arrival flags of the group, then the go word
+  int* err;
+  const FdTables* fdt;
+  int64_t ng, nchunk;
+  double dv, kT, cn, Ne, lam;
+  int xc;
+  double eta0, tol;
+  int mixing, warmup;
+  double trust;
+  int max_newton;
+  int max_iter;  // the iteration that reaches it is the last (done is raised)
+};
+
+// The rest of an iteration is a fixed sequence of steps; a step that does not
+// apply to a system (no von Weizsaecker term, fixed mixing) is left out of its
+// list.  The slot says where a step sits in the sequence, so the batched driver
+// can run slot s of every system in one launch.
+enum {
+  SLOT_NHAT_A = 0,     // 3 passes: R2C(n_a) -> n^_a with the U_H partials
+  SLOT_LAP_A = 3,      // 3 passes: R2C(sqrt n_a) with the Laplacian (More + vW)
+  SLOT_UVW = 6,        // 3 passes: C2R summing U_vW (More + vW)
+  SLOT_WEIGHT = 9,     // the mixing weight
+  SLOT_HARTREE = 10,   // 3 passes: C2R of n_o^/(pi k^2) forming n_o^ -> V_H
+  SLOT_SQRT_O = 13,    // 3 passes: R2C(sqrt n_o) forming n_o, Laplacian (vW)
+  SLOT_LAP_O = 16,     // 3 passes: C2R -> lap sqrt(n_o) (vW)
+  SLOT_REAL_MIX = 19,  // n_o in real space (no vW)
+  SLOT_COUNT = 20
+};
+enum { STEP_FFT = 0, STEP_WEIGHT = 1, STEP_REAL_MIX = 2 };
+struct MixWeightArgs {
+  ScfState* st;
+  const double* part_h;
+  int nbh;
+  const double* part_v;
+  int nbv;
+  int use_vw;
+  double vol, dv, w_fixed;
+};
+struct RealMixArgs {
+  const ScfState* st;
+  double* n_i;
+  const double* n_a;
+  double* sq;
+  int64_t ng;
+};
+struct IterStep {
+  int slot, kind;
+  unsigned nblocks;
+  FftPass fft;
+  MixWeightArgs mw;
+  RealMixArgs rm;
+};
+
 struct arche_ctx {
   arche_params p;  // copy; pointer members are not kept
   std::vector<int32_t> species;
@@ -59,6 +124,7 @@ struct arche_ctx {
   SpeciesInfo sp{};
   FftPlan plan{};
   hipStream_t stream = nullptr;
+  bool own_stream = false;
   int device = 0;
   int coop_blocks = 0;
   std::string err;
@@ -100,6 +166,10 @@ struct arche_ctx {
   bool have_r_prev = false;
   // optional per-kernel timing
   Profiler* prof = nullptr;
+  // launch arguments of an iteration (fixed for the life of the context)
+  bool iter_built = false, fused = false;
+  ActiveArgs active{};
+  std::vector<IterStep> steps;
 };
 
 // device Fermi-Dirac tables (uploaded once per process and device)
@@ -119,6 +189,17 @@ hipError_t scf_initial_uniform(arche_ctx* c);
 hipError_t scf_initial_one_center(arche_ctx* c, int* used_fallback);  // ionic.hip
 hipError_t scf_prepare_input(arche_ctx* c);  // n^_i, V_H, lap sqrt(n_i) from n_i
 int scf_coop_blocks(int64_t ng);
+// the iteration's launch arguments (fills c->active, c->steps, c->fused)
+void scf_build_iteration(arche_ctx* c);
+hipError_t scf_step_launch(const IterStep& st, hipStream_t s);
+// batched forms (one launch for many systems)
+int scf_batch_capacity();  // co-resident blocks of the batched cooperative kernel
+hipError_t scf_active_batch_launch(const ActiveArgs* args, const int* group_begin, int nsys, int nblocks,
+                                   hipStream_t s);
+hipError_t scf_weight_batch_launch(const MixWeightArgs* jobs, int njobs, hipStream_t s);
+hipError_t scf_real_mix_batch_launch(const RealMixArgs* jobs, const int* bbeg, int njobs, unsigned nblocks,
+                                     hipStream_t s);
+unsigned scf_real_mix_blocks(int64_t ng);
 size_t scf_part_offset(const arche_ctx* c);  // start of the non-cooperative partials
 
 // ionic (ionic.hip)
@@ -129,3 +210,10 @@ hipError_t ionic_pressure_ie(arche_ctx* c, const cplx* nhat, double* out /*host*
 hipError_t ionic_shells(arche_ctx* c);
 size_t ionic_force_partials(const arche_ctx* c);
 double ewald_alpha(const arche_ctx* c);
+
+// runtime.hip: the phases of one solve, shared with the batched driver
+arche_status solve_begin(arche_ctx* c, const double* pos_host, int init, int* fallback);  // ionic field, guess, reset
+arche_status solve_collect(arche_ctx* c, arche_result* out);  // SCF state -> out
+arche_status solve_finish(arche_ctx* c, arche_result* out, int fallback);  // energies, pressure, history
+arche_status solve_forces(arche_ctx* c);  // forces -> c->h_forces
+arche_status ctx_error(arche_ctx* c, arche_status s, const std::string& m);

@@ -56,7 +56,70 @@ struct FftFuse {
   double* partials;      // one double per block of the fused pass
   double lam;            // C2R_OUT_UVW
   double L[3];           // cell edges, for |k|
+  const int* stop;       // device flag: when nonzero the pass does nothing (null: always run)
 };
+// k-vector helpers of the x pass: element k of column `line` in the tile at outer
+// index o (the y index) is the point (m_x = k, m_y = o, m_z = c0 + line).
+struct XGeom {
+  int Nx, Ny, Nz;
+  double Lx, Ly, Lz;
+  __device__ double k2(int mx, int my, int mz) const {
+    const double kx = (double)(mx <= Nx / 2 ? mx : mx - Nx) / Lx;
+    const double ky = (double)(my <= Ny / 2 ? my : my - Ny) / Ly;
+    const double kz = (double)mz / Lz;
+    return kx * kx + ky * ky + kz * kz;
+  }
+  __device__ double weight(int mz) const { return (mz == 0 || 2 * mz == Nz) ? 1.0 : 2.0; }
+};
+
+// Arguments of one strided pass (lines along y or x of the half spectrum).
+struct StridedArgs {
+  cplx* data;        // transformed in place (MODE 3: the work array)
+  const cplx* src;   // MODE 3: the input spectrum
+  const cplx* tw;    // [L] exp(-2 pi i m / L)
+  int64_t es, os;    // element stride along the line, stride between outer indices
+  int ncols, nchunk; // columns (k_z values) per outer index, tiles of TK columns
+  double scale;
+  FftFuse f;
+  XGeom g;
+};
+
+// Arguments of one z pass: rows of the real field paired into complex lines.
+struct ZArgs {
+  const void* in;    // R2C: real [ng]; C2R: half spectrum [nh]
+  void* out;         // R2C: half spectrum; C2R: real field
+  const cplx* tw;    // [L]
+  int64_t npairs;    // Nx*Ny/2
+  double in_scale, out_scale;
+  FftFuse f;
+};
+
+// One pass of a compile-time transform: what a single-grid launch takes, and the
+// job a batched launch runs for one grid.
+enum { FFT_PASS_STRIDED = 0, FFT_PASS_Z_R2C = 1, FFT_PASS_Z_C2R = 2 };
+struct FftPass {
+  int kind;        // FFT_PASS_*
+  int L;           // line length
+  int sign, mode;  // strided: transform sign and MODE; z passes: FIN or FOUT code
+  unsigned nblocks;
+  StridedArgs s;   // FFT_PASS_STRIDED
+  ZArgs z;         // the z passes
+};
+// The three passes of a fused transform (fft_r2c_fused / fft_c2r_fused with the
+// same arguments); false if the plan has no compile-time kernels.
+bool fft_r2c_passes(const FftPlan* p, const double* in, cplx* out, double in_scale, double out_scale, int fin, int fout,
+                    const FftFuse& f, FftPass out3[3]);
+bool fft_c2r_passes(const FftPlan* p, const cplx* in, cplx* work, double* out, double out_scale, int fin, int fout,
+                    const FftFuse& f, FftPass out3[3]);
+hipError_t fft_pass_launch(const FftPass& ps, hipStream_t s);
+
+// Batched passes (fft_batch.hip): one launch runs the jobs[j] (device array of
+// FftPass, all of the same kind, sign and mode, line lengths within
+// fft_batch_supported) with job j owning blocks [bbeg[j], bbeg[j+1]).
+bool fft_batch_supported(int L);
+hipError_t fft_batch_launch(int kind, int sign, int mode, const FftPass* jobs, const int* bbeg, int njobs,
+                            unsigned nblocks, hipStream_t s);
+
 bool fft_fusable(const FftPlan* p);
 // number of blocks (= partial sums) of the fused x pass and of the fused z pass
 int fft_x_blocks(const FftPlan* p);

@@ -1,6 +1,6 @@
 // FP64 3D real<->complex FFT for gfx950 (see fft.h for the layout and passes).
 #include "fft.h"
-#include "fft_plans.h"
+#include "fft_bodies.h"
 #include "profile.h"
 
 #include <cmath>
@@ -8,6 +8,8 @@
 #include <vector>
 
 namespace {
+
+using namespace fftct;
 
 struct Radices {
   int nst;
@@ -250,348 +252,55 @@ k_fft_strided(cplx* __restrict__ data, const cplx* __restrict__ tw_g, int L, int
 }
 
 // ---------------------------------------------------------------------------
-// Compile-time kernels (fft_plans.h) for the supported line lengths.
-using namespace fftct;
+// Compile-time kernels (fft_plans.h, tile bodies in fft_bodies.h) for the
+// supported line lengths.  A pass whose FftFuse names a stop flag does nothing
+// once it is set (a converged SCF).
+__device__ inline bool fft_stopped(const FftFuse& f) { return f.stop && *f.stop; }
 
-struct ColIn {  // column tile of a strided pass: element k of column `line`
-  const cplx* base;
-  int64_t es;
-  int nc;
-  __device__ cplx operator()(int line, int k) const { return line < nc ? base[(int64_t)k * es + line] : cplx{0.0, 0.0}; }
-};
-struct ColOut {
-  cplx* base;
-  int64_t es;
-  int nc;
-  double scale;
-  __device__ void operator()(int line, int k, cplx v) const {
-    if (line < nc) base[(int64_t)k * es + line] = cscale(v, scale);
-  }
-  __device__ void barrier_before() const {}
-  __device__ void barrier_after() const {}
-};
-
-// k-vector helpers of the x pass: element k of column `line` in the tile at outer
-// index o (the y index) is the point (m_x = k, m_y = o, m_z = c0 + line).
-struct XGeom {
-  int Nx, Ny, Nz;
-  double Lx, Ly, Lz;
-  __device__ double k2(int mx, int my, int mz) const {
-    const double kx = (double)(mx <= Nx / 2 ? mx : mx - Nx) / Lx;
-    const double ky = (double)(my <= Ny / 2 ? my : my - Ny) / Ly;
-    const double kz = (double)mz / Lz;
-    return kx * kx + ky * ky + kz * kz;
-  }
-  __device__ double weight(int mz) const { return (mz == 0 || 2 * mz == Nz) ? 1.0 : 2.0; }
-};
-
-struct ColOutLap {  // R2C_OUT_LAP
-  cplx* base;
-  int64_t es;
-  int nc;
-  double scale;
-  XGeom g;
-  int o, c0;
-  __device__ void operator()(int line, int k, cplx v) const {
-    if (line >= nc) return;
-    const double q2 = 39.478417604357434 * g.k2(k, o, c0 + line);  // (2 pi)^2 |k|^2
-    base[(int64_t)k * es + line] = cscale(v, -q2 * scale);
-  }
-  __device__ void barrier_before() const {}
-  __device__ void barrier_after() const {}
-};
-
-struct ColOutUH {  // R2C_OUT_UH
-  cplx* base;
-  const cplx* nhat_i;
-  int64_t es;
-  int nc;
-  double scale;
-  XGeom g;
-  int o, c0;
-  double* acc;
-  __device__ void operator()(int line, int k, cplx v) const {
-    if (line >= nc) return;
-    const int64_t at = (int64_t)k * es + line;
-    const cplx a = cscale(v, scale);
-    base[at] = a;
-    const double k2 = g.k2(k, o, c0 + line);
-    if (k2 > 0.0) {
-      const cplx d = csub(nhat_i[at], a);
-      *acc += g.weight(c0 + line) * (d.x * d.x + d.y * d.y) / (3.14159265358979323846 * k2);
-    }
-  }
-  __device__ void barrier_before() const {}
-  __device__ void barrier_after() const {}
-};
-
-struct ColInMix {  // C2R_IN_MIX: n_o^ = a + w (nhat_i - a); nhat_i <- n_o^; value n_o^/(pi k^2)
-  const cplx* a;
-  cplx* nhat_i;
-  int64_t es;
-  int nc;
-  double w;
-  XGeom g;
-  int o, c0;
-  __device__ cplx operator()(int line, int k) const {
-    if (line >= nc) return cplx{0.0, 0.0};
-    const int64_t at = (int64_t)k * es + line;
-    const cplx x = a[at];
-    const cplx no = cadd(x, cscale(csub(nhat_i[at], x), w));
-    nhat_i[at] = no;
-    const double k2 = g.k2(k, o, c0 + line);
-    return k2 > 0.0 ? cscale(no, 1.0 / (3.14159265358979323846 * k2)) : cplx{0.0, 0.0};
-  }
-};
-
-// MODE 0: plain in-place pass.  MODE 1/2/3: x pass with R2C_OUT_LAP / R2C_OUT_UH /
-// C2R_IN_MIX (then `src` is the input spectrum and `data` the work array).
 template <int L, int TK, int S, int MODE>
-__global__ void __launch_bounds__(ARCHE_BLOCK)
-k_strided_ct(cplx* __restrict__ data, const cplx* __restrict__ src, const cplx* __restrict__ tw_g, int64_t es,
-             int64_t os, int ncols, int nchunk, double scale, FftFuse f, XGeom g) {
-  constexpr int NS = nstages(typename Plan<L>::R{});
-  __shared__ cplx lds[NS > 1 ? lds_size<L, TK, true>() : 1];
+__global__ void __launch_bounds__(ARCHE_BLOCK) k_strided_ct(StridedArgs A) {
+  if (fft_stopped(A.f)) return;
+  __shared__ cplx lds[strided_lds<L, TK>()];
   __shared__ cplx tw[L];
   __shared__ double sh[ARCHE_BLOCK / 64];
-  for (int i = threadIdx.x; i < L; i += ARCHE_BLOCK) tw[i] = tw_g[i];
-  __syncthreads();
-  const int o = blockIdx.x / nchunk;
-  const int c0 = (blockIdx.x - o * nchunk) * TK;
-  const int nc = (ncols - c0) < TK ? (ncols - c0) : TK;
-  cplx* base = data + (int64_t)o * os + c0;
-  if constexpr (MODE == 0) {
-    run<L, TK, ARCHE_BLOCK, true, S, 1>(ColIn{base, es, nc}, ColOut{base, es, nc, scale}, lds, tw, nc,
-                                         typename Plan<L>::R{});
-  } else if constexpr (MODE == 1) {
-    run<L, TK, ARCHE_BLOCK, true, S, 1>(ColIn{base, es, nc}, ColOutLap{base, es, nc, scale, g, o, c0}, lds, tw, nc,
-                                         typename Plan<L>::R{});
-  } else if constexpr (MODE == 2) {
-    double acc = 0.0;
-    run<L, TK, ARCHE_BLOCK, true, S, 1>(ColIn{base, es, nc},
-                                         ColOutUH{base, f.nhat_i + (int64_t)o * os + c0, es, nc, scale, g, o, c0, &acc},
-                                         lds, tw, nc, typename Plan<L>::R{});
-    acc = block_sum(acc, sh);
-    if (threadIdx.x == 0) f.partials[blockIdx.x] = acc;
-  } else {
-    const int64_t off = (int64_t)o * os + c0;
-    run<L, TK, ARCHE_BLOCK, true, S, 1>(ColInMix{src + off, f.nhat_i + off, es, nc, *f.w, g, o, c0},
-                                         ColOut{base, es, nc, scale}, lds, tw, nc, typename Plan<L>::R{});
-  }
+  strided_body<L, TK, S, MODE>(A, blockIdx.x, lds, tw, sh);
 }
-
-struct PairIn {  // two real rows packed as one complex line
-  const double* src;
-  int L;
-  int nv;
-  double s;
-  __device__ cplx operator()(int line, int k) const {
-    if (line >= nv) return cplx{0.0, 0.0};
-    const double* r0 = src + (int64_t)line * 2 * L;
-    return cplx{r0[k] * s, r0[L + k] * s};
-  }
-};
-struct PairInSqrt {  // R2C_IN_SQRT
-  const double* src;
-  int L;
-  int nv;
-  double s;
-  __device__ cplx operator()(int line, int k) const {
-    if (line >= nv) return cplx{0.0, 0.0};
-    const double* r0 = src + (int64_t)line * 2 * L;
-    return cplx{sqrt(r0[k]) * s, sqrt(r0[L + k]) * s};
-  }
-};
-struct PairInMix {  // R2C_IN_MIX_SQRT: n_o = n_a + w (n_i - n_a); n_i <- n_o; sqrt(n_o)
-  const double* na;
-  double* ni;
-  int L;
-  int nv;
-  double s, w;
-  __device__ double one(int64_t at) const {
-    const double a = na[at];
-    const double o = a + w * (ni[at] - a);
-    ni[at] = o;
-    return sqrt(o) * s;
-  }
-  __device__ cplx operator()(int line, int k) const {
-    if (line >= nv) return cplx{0.0, 0.0};
-    const int64_t at = (int64_t)line * 2 * L + k;
-    return cplx{one(at), one(at + L)};
-  }
-};
 
 template <int L, int B, int FIN>
-__global__ void __launch_bounds__(ARCHE_BLOCK)
-k_z_r2c_ct(const double* __restrict__ in, cplx* __restrict__ out, const cplx* __restrict__ tw_g, int64_t npairs,
-           double in_scale, double out_scale, FftFuse f) {
-  constexpr int Nh = L / 2 + 1;
-  __shared__ cplx lds[lds_size<L, B, false>()];
+__global__ void __launch_bounds__(ARCHE_BLOCK) k_z_r2c_ct(ZArgs A) {
+  if (fft_stopped(A.f)) return;
+  __shared__ cplx lds[z_r2c_lds<L, B>()];
   __shared__ cplx tw[L];
-  for (int i = threadIdx.x; i < L; i += ARCHE_BLOCK) tw[i] = tw_g[i];
-  __syncthreads();
-  const int64_t p0 = (int64_t)blockIdx.x * B;
-  const int nb = (int)((npairs - p0) < B ? (npairs - p0) : B);
-  LdsIO<L, B, false> res{lds};
-  if constexpr (FIN == 0)
-    run<L, B, ARCHE_BLOCK, false, -1, 1>(PairIn{in + p0 * 2 * L, L, nb, in_scale}, res, lds, tw, nb,
-                                          typename Plan<L>::R{});
-  else if constexpr (FIN == 1)
-    run<L, B, ARCHE_BLOCK, false, -1, 1>(PairInSqrt{in + p0 * 2 * L, L, nb, in_scale}, res, lds, tw, nb,
-                                          typename Plan<L>::R{});
-  else
-    run<L, B, ARCHE_BLOCK, false, -1, 1>(PairInMix{in + p0 * 2 * L, f.n_i + p0 * 2 * L, L, nb, in_scale, *f.w}, res,
-                                          lds, tw, nb, typename Plan<L>::R{});
-  cplx* dst = out + p0 * 2 * Nh;
-  for (int q = threadIdx.x; q < nb * 2 * Nh; q += ARCHE_BLOCK) {
-    const int l = q / (2 * Nh);
-    const int w = q - l * 2 * Nh;
-    const int r = w / Nh;
-    const int k = w - r * Nh;
-    const cplx zk = res(l, k);
-    const cplx zn = res(l, k == 0 ? 0 : L - k);
-    cplx v;
-    if (r == 0)
-      v = cplx{0.5 * (zk.x + zn.x), 0.5 * (zk.y - zn.y)};
-    else
-      v = cplx{0.5 * (zk.y + zn.y), -0.5 * (zk.x - zn.x)};
-    dst[q] = cscale(v, out_scale);
-  }
+  z_r2c_body<L, B, FIN>(A, blockIdx.x, lds, tw);
 }
-
-struct HermIn {  // Z_k = X_k + i Y_k from the half spectra of two real rows
-  const cplx* src;
-  int L, Nh, nv;
-  __device__ cplx operator()(int line, int k) const {
-    if (line >= nv) return cplx{0.0, 0.0};
-    const cplx* X = src + (int64_t)line * 2 * Nh;
-    const cplx* Y = X + Nh;
-    cplx x, y;
-    if (k == 0 || 2 * k == L) {
-      x = cplx{X[k].x, 0.0};
-      y = cplx{Y[k].x, 0.0};
-    } else if (2 * k < L) {
-      x = X[k];
-      y = Y[k];
-    } else {
-      x = cconj(X[L - k]);
-      y = cconj(Y[L - k]);
-    }
-    return cplx{x.x - y.y, x.y + y.x};
-  }
-};
-struct PairOut {
-  double* dst;
-  int L, nv;
-  double scale;
-  __device__ void operator()(int line, int k, cplx v) const {
-    if (line >= nv) return;
-    double* r0 = dst + (int64_t)line * 2 * L;
-    r0[k] = v.x * scale;
-    r0[L + k] = v.y * scale;
-  }
-  __device__ void barrier_before() const {}
-  __device__ void barrier_after() const {}
-};
-
-struct PairOutUvw {  // C2R_OUT_UVW: accumulate (v_vW[n_i] - v_vW[n_a]) (n_i - n_a), no store
-  const double* ni;
-  const double* lapi;
-  const double* na;
-  int L, nv;
-  double scale, hl;  // hl = lambda/2
-  double* acc;
-  __device__ void one(int64_t at, double lap) const {
-    const double a = ni[at], b = na[at];
-    const double vi = -hl * lapi[at] / sqrt(a);
-    const double va = -hl * lap / sqrt(b);
-    *acc += (vi - va) * (a - b);
-  }
-  __device__ void operator()(int line, int k, cplx v) const {
-    if (line >= nv) return;
-    const int64_t at = (int64_t)line * 2 * L + k;
-    one(at, v.x * scale);
-    one(at + L, v.y * scale);
-  }
-  __device__ void barrier_before() const {}
-  __device__ void barrier_after() const {}
-};
 
 template <int L, int B, int FOUT>
-__global__ void __launch_bounds__(ARCHE_BLOCK)
-k_z_c2r_ct(const cplx* __restrict__ in, double* __restrict__ out, const cplx* __restrict__ tw_g, int64_t npairs,
-           double out_scale, FftFuse f) {
-  constexpr int Nh = L / 2 + 1;
-  constexpr int NS = nstages(typename Plan<L>::R{});
-  __shared__ cplx lds[NS > 1 ? lds_size<L, B, false>() : 1];
+__global__ void __launch_bounds__(ARCHE_BLOCK) k_z_c2r_ct(ZArgs A) {
+  if (fft_stopped(A.f)) return;
+  __shared__ cplx lds[z_c2r_lds<L, B>()];
   __shared__ cplx tw[L];
   __shared__ double sh[ARCHE_BLOCK / 64];
-  for (int i = threadIdx.x; i < L; i += ARCHE_BLOCK) tw[i] = tw_g[i];
-  __syncthreads();
-  const int64_t p0 = (int64_t)blockIdx.x * B;
-  const int nb = (int)((npairs - p0) < B ? (npairs - p0) : B);
-  if constexpr (FOUT == 0) {
-    run<L, B, ARCHE_BLOCK, false, +1, 1>(HermIn{in + p0 * 2 * Nh, L, Nh, nb},
-                                          PairOut{out + p0 * 2 * L, L, nb, out_scale}, lds, tw, nb,
-                                          typename Plan<L>::R{});
+  z_c2r_body<L, B, FOUT>(A, blockIdx.x, lds, tw, sh);
+}
+
+template <int L>
+hipError_t launch_pass(const FftPass& ps, hipStream_t s) {
+  constexpr int B = ct_rows<L>();
+  const dim3 grid(ps.nblocks), blk(ARCHE_BLOCK);
+  if (ps.kind == FFT_PASS_STRIDED) {
+    if (ps.mode == 0 && ps.sign < 0) hipLaunchKernelGGL((k_strided_ct<L, CT_TK, -1, 0>), grid, blk, 0, s, ps.s);
+    else if (ps.mode == 0) hipLaunchKernelGGL((k_strided_ct<L, CT_TK, +1, 0>), grid, blk, 0, s, ps.s);
+    else if (ps.mode == 1) hipLaunchKernelGGL((k_strided_ct<L, CT_TK, -1, 1>), grid, blk, 0, s, ps.s);
+    else if (ps.mode == 2) hipLaunchKernelGGL((k_strided_ct<L, CT_TK, -1, 2>), grid, blk, 0, s, ps.s);
+    else hipLaunchKernelGGL((k_strided_ct<L, CT_TK, +1, 3>), grid, blk, 0, s, ps.s);
+  } else if (ps.kind == FFT_PASS_Z_R2C) {
+    if (ps.mode == 0) hipLaunchKernelGGL((k_z_r2c_ct<L, B, 0>), grid, blk, 0, s, ps.z);
+    else if (ps.mode == 1) hipLaunchKernelGGL((k_z_r2c_ct<L, B, 1>), grid, blk, 0, s, ps.z);
+    else hipLaunchKernelGGL((k_z_r2c_ct<L, B, 2>), grid, blk, 0, s, ps.z);
   } else {
-    double acc = 0.0;
-    const int64_t off = p0 * 2 * L;
-    run<L, B, ARCHE_BLOCK, false, +1, 1>(
-        HermIn{in + p0 * 2 * Nh, L, Nh, nb},
-        PairOutUvw{f.n_i + off, f.lap_i + off, f.n_a + off, L, nb, out_scale, 0.5 * f.lam, &acc}, lds, tw, nb,
-        typename Plan<L>::R{});
-    acc = block_sum(acc, sh);
-    if (threadIdx.x == 0) f.partials[blockIdx.x] = acc;
+    if (ps.mode == 0) hipLaunchKernelGGL((k_z_c2r_ct<L, B, 0>), grid, blk, 0, s, ps.z);
+    else hipLaunchKernelGGL((k_z_c2r_ct<L, B, 1>), grid, blk, 0, s, ps.z);
   }
-}
-
-constexpr int CT_TK = 16;
-template <int L>
-constexpr int ct_rows() {
-  return L >= 96 ? 16 : 32;
-}
-
-template <int L, int S, int MODE>
-hipError_t launch_strided_ct(cplx* data, const cplx* src, const cplx* tw, int64_t es, int64_t os, int nouter, int ncols,
-                             double scale, const FftFuse& f, const XGeom& g, hipStream_t s) {
-  const int nchunk = (ncols + CT_TK - 1) / CT_TK;
-  hipLaunchKernelGGL((k_strided_ct<L, CT_TK, S, MODE>), dim3(nouter * nchunk), dim3(ARCHE_BLOCK), 0, s, data, src, tw,
-                     es, os, ncols, nchunk, scale, f, g);
-  return hipGetLastError();
-}
-template <int L>
-hipError_t launch_strided_mode(int mode, int sign, cplx* data, const cplx* src, const cplx* tw, int64_t es, int64_t os,
-                               int nouter, int ncols, double scale, const FftFuse& f, const XGeom& g, hipStream_t s) {
-  if (mode == 0)
-    return sign < 0 ? launch_strided_ct<L, -1, 0>(data, src, tw, es, os, nouter, ncols, scale, f, g, s)
-                    : launch_strided_ct<L, +1, 0>(data, src, tw, es, os, nouter, ncols, scale, f, g, s);
-  if (mode == 1) return launch_strided_ct<L, -1, 1>(data, src, tw, es, os, nouter, ncols, scale, f, g, s);
-  if (mode == 2) return launch_strided_ct<L, -1, 2>(data, src, tw, es, os, nouter, ncols, scale, f, g, s);
-  return launch_strided_ct<L, +1, 3>(data, src, tw, es, os, nouter, ncols, scale, f, g, s);
-}
-template <int L>
-hipError_t launch_z_r2c_ct(int fin, const double* in, cplx* out, const cplx* tw, int64_t npairs, double is, double os,
-                           const FftFuse& f, hipStream_t s) {
-  constexpr int B = ct_rows<L>();
-  const dim3 grid((unsigned)((npairs + B - 1) / B));
-  if (fin == 0)
-    hipLaunchKernelGGL((k_z_r2c_ct<L, B, 0>), grid, dim3(ARCHE_BLOCK), 0, s, in, out, tw, npairs, is, os, f);
-  else if (fin == 1)
-    hipLaunchKernelGGL((k_z_r2c_ct<L, B, 1>), grid, dim3(ARCHE_BLOCK), 0, s, in, out, tw, npairs, is, os, f);
-  else
-    hipLaunchKernelGGL((k_z_r2c_ct<L, B, 2>), grid, dim3(ARCHE_BLOCK), 0, s, in, out, tw, npairs, is, os, f);
-  return hipGetLastError();
-}
-template <int L>
-hipError_t launch_z_c2r_ct(int fout, const cplx* in, double* out, const cplx* tw, int64_t npairs, double os,
-                           const FftFuse& f, hipStream_t s) {
-  constexpr int B = ct_rows<L>();
-  const dim3 grid((unsigned)((npairs + B - 1) / B));
-  if (fout == 0)
-    hipLaunchKernelGGL((k_z_c2r_ct<L, B, 0>), grid, dim3(ARCHE_BLOCK), 0, s, in, out, tw, npairs, os, f);
-  else
-    hipLaunchKernelGGL((k_z_c2r_ct<L, B, 1>), grid, dim3(ARCHE_BLOCK), 0, s, in, out, tw, npairs, os, f);
   return hipGetLastError();
 }
 template <int L>
@@ -615,36 +324,11 @@ bool ct_supported(int L) {
   }
 }
 
-hipError_t ct_strided(int L, int mode, int sign, cplx* data, const cplx* src, const cplx* tw, int64_t es, int64_t os,
-                      int nouter, int ncols, double scale, const FftFuse& f, const XGeom& g, hipStream_t s) {
-  switch (L) {
+hipError_t launch_pass_any(const FftPass& ps, hipStream_t s) {
+  switch (ps.L) {
 #define X(n) \
   case n:    \
-    return launch_strided_mode<n>(mode, sign, data, src, tw, es, os, nouter, ncols, scale, f, g, s);
-    ARCHE_CT_SIZES(X)
-#undef X
-    default:
-      return hipErrorNotSupported;
-  }
-}
-hipError_t ct_z_r2c(int L, int fin, const double* in, cplx* out, const cplx* tw, int64_t npairs, double is, double os,
-                    const FftFuse& f, hipStream_t s) {
-  switch (L) {
-#define X(n) \
-  case n:    \
-    return launch_z_r2c_ct<n>(fin, in, out, tw, npairs, is, os, f, s);
-    ARCHE_CT_SIZES(X)
-#undef X
-    default:
-      return hipErrorNotSupported;
-  }
-}
-hipError_t ct_z_c2r(int L, int fout, const cplx* in, double* out, const cplx* tw, int64_t npairs, double os,
-                    const FftFuse& f, hipStream_t s) {
-  switch (L) {
-#define X(n) \
-  case n:    \
-    return launch_z_c2r_ct<n>(fout, in, out, tw, npairs, os, f, s);
+    return launch_pass<n>(ps, s);
     ARCHE_CT_SIZES(X)
 #undef X
     default:
@@ -661,6 +345,47 @@ int ct_z_rows(int L) {
     default:
       return 0;
   }
+}
+
+FftPass strided_desc(int L, int mode, int sign, cplx* data, const cplx* src, const cplx* tw, int64_t es, int64_t os,
+                     int nouter, int ncols, double scale, const FftFuse& f, const XGeom& g) {
+  FftPass ps{};
+  ps.kind = FFT_PASS_STRIDED;
+  ps.L = L;
+  ps.sign = sign;
+  ps.mode = mode;
+  const int nchunk = (ncols + CT_TK - 1) / CT_TK;
+  ps.nblocks = (unsigned)(nouter * nchunk);
+  ps.s = StridedArgs{data, src, tw, es, os, ncols, nchunk, scale, f, g};
+  return ps;
+}
+FftPass z_desc(int kind, int L, int code, const void* in, void* out, const cplx* tw, int64_t npairs, double is,
+               double os, const FftFuse& f) {
+  FftPass ps{};
+  ps.kind = kind;
+  ps.L = L;
+  ps.sign = kind == FFT_PASS_Z_R2C ? -1 : +1;
+  ps.mode = code;
+  const int B = ct_z_rows(L);
+  ps.nblocks = (unsigned)((npairs + B - 1) / B);
+  ps.z = ZArgs{in, out, tw, npairs, is, os, f};
+  return ps;
+}
+
+hipError_t ct_strided(int L, int mode, int sign, cplx* data, const cplx* src, const cplx* tw, int64_t es, int64_t os,
+                      int nouter, int ncols, double scale, const FftFuse& f, const XGeom& g, hipStream_t s) {
+  if (!ct_supported(L)) return hipErrorNotSupported;
+  return launch_pass_any(strided_desc(L, mode, sign, data, src, tw, es, os, nouter, ncols, scale, f, g), s);
+}
+hipError_t ct_z_r2c(int L, int fin, const double* in, cplx* out, const cplx* tw, int64_t npairs, double is, double os,
+                    const FftFuse& f, hipStream_t s) {
+  if (!ct_supported(L)) return hipErrorNotSupported;
+  return launch_pass_any(z_desc(FFT_PASS_Z_R2C, L, fin, in, out, tw, npairs, is, os, f), s);
+}
+hipError_t ct_z_c2r(int L, int fout, const cplx* in, double* out, const cplx* tw, int64_t npairs, double os,
+                    const FftFuse& f, hipStream_t s) {
+  if (!ct_supported(L)) return hipErrorNotSupported;
+  return launch_pass_any(z_desc(FFT_PASS_Z_C2R, L, fout, in, out, tw, npairs, 1.0, os, f), s);
 }
 
 Radices radices_of(const FftAxis& ax) {
@@ -822,45 +547,54 @@ static XGeom xgeom(const FftPlan* p, const FftFuse& f) {
   return XGeom{p->N[0], p->N[1], p->N[2], f.L[0], f.L[1], f.L[2]};
 }
 
-hipError_t fft_r2c_fused(const FftPlan* p, const double* in, cplx* out, double in_scale, double out_scale, int fin,
-                         int fout, const FftFuse& f, hipStream_t s) {
-  if (!fft_fusable(p)) return hipErrorNotSupported;
+bool fft_r2c_passes(const FftPlan* p, const double* in, cplx* out, double in_scale, double out_scale, int fin, int fout,
+                    const FftFuse& f, FftPass o[3]) {
+  if (!fft_fusable(p)) return false;
   const int64_t npairs = (int64_t)p->N[0] * p->N[1] / 2;
   const int Nh = p->Nh;
-  hipError_t e;
-  {
-    ProfScope prof(PROF_FFT_Z, s);
-    e = ct_z_r2c(p->N[2], fin, in, out, p->ax[2].tw, npairs, in_scale, 1.0, f, s);
-  }
-  if (e != hipSuccess) return e;
-  {
-    ProfScope prof(PROF_FFT_STRIDED, s);
-    e = ct_strided(p->N[1], 0, -1, out, out, p->ax[1].tw, Nh, (int64_t)p->N[1] * Nh, p->N[0], Nh, 1.0, f, XGeom{}, s);
-  }
-  if (e != hipSuccess) return e;
-  ProfScope prof(PROF_FFT_STRIDED, s);
+  o[0] = z_desc(FFT_PASS_Z_R2C, p->N[2], fin, in, out, p->ax[2].tw, npairs, in_scale, 1.0, f);
+  o[1] = strided_desc(p->N[1], 0, -1, out, out, p->ax[1].tw, Nh, (int64_t)p->N[1] * Nh, p->N[0], Nh, 1.0, f, XGeom{});
   const int mode = fout == R2C_OUT_LAP ? 1 : (fout == R2C_OUT_UH ? 2 : 0);
-  return ct_strided(p->N[0], mode, -1, out, out, p->ax[0].tw, (int64_t)p->N[1] * Nh, Nh, p->N[1], Nh, out_scale, f,
-                    xgeom(p, f), s);
+  o[2] = strided_desc(p->N[0], mode, -1, out, out, p->ax[0].tw, (int64_t)p->N[1] * Nh, Nh, p->N[1], Nh, out_scale, f,
+                      xgeom(p, f));
+  return true;
+}
+
+bool fft_c2r_passes(const FftPlan* p, const cplx* in, cplx* work, double* out, double out_scale, int fin, int fout,
+                    const FftFuse& f, FftPass o[3]) {
+  if (!fft_fusable(p)) return false;
+  const int64_t npairs = (int64_t)p->N[0] * p->N[1] / 2;
+  const int Nh = p->Nh;
+  o[0] = strided_desc(p->N[0], fin == C2R_IN_MIX ? 3 : 0, +1, work, fin == C2R_IN_MIX ? in : work, p->ax[0].tw,
+                      (int64_t)p->N[1] * Nh, Nh, p->N[1], Nh, 1.0, f, xgeom(p, f));
+  o[1] = strided_desc(p->N[1], 0, +1, work, work, p->ax[1].tw, Nh, (int64_t)p->N[1] * Nh, p->N[0], Nh, 1.0, f, XGeom{});
+  o[2] = z_desc(FFT_PASS_Z_C2R, p->N[2], fout, work, out, p->ax[2].tw, npairs, 1.0, out_scale, f);
+  return true;
+}
+
+hipError_t fft_pass_launch(const FftPass& ps, hipStream_t s) {
+  ProfScope prof(ps.kind == FFT_PASS_STRIDED ? PROF_FFT_STRIDED : PROF_FFT_Z, s);
+  return launch_pass_any(ps, s);
+}
+
+hipError_t fft_r2c_fused(const FftPlan* p, const double* in, cplx* out, double in_scale, double out_scale, int fin,
+                         int fout, const FftFuse& f, hipStream_t s) {
+  FftPass ps[3];
+  if (!fft_r2c_passes(p, in, out, in_scale, out_scale, fin, fout, f, ps)) return hipErrorNotSupported;
+  for (int i = 0; i < 3; ++i) {
+    hipError_t e = fft_pass_launch(ps[i], s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t fft_c2r_fused(const FftPlan* p, const cplx* in, cplx* work, double* out, double out_scale, int fin, int fout,
                          const FftFuse& f, hipStream_t s) {
-  if (!fft_fusable(p)) return hipErrorNotSupported;
-  const int64_t npairs = (int64_t)p->N[0] * p->N[1] / 2;
-  const int Nh = p->Nh;
-  hipError_t e;
-  {
-    ProfScope prof(PROF_FFT_STRIDED, s);
-    e = ct_strided(p->N[0], fin == C2R_IN_MIX ? 3 : 0, +1, work, fin == C2R_IN_MIX ? in : work, p->ax[0].tw,
-                   (int64_t)p->N[1] * Nh, Nh, p->N[1], Nh, 1.0, f, xgeom(p, f), s);
+  FftPass ps[3];
+  if (!fft_c2r_passes(p, in, work, out, out_scale, fin, fout, f, ps)) return hipErrorNotSupported;
+  for (int i = 0; i < 3; ++i) {
+    hipError_t e = fft_pass_launch(ps[i], s);
+    if (e != hipSuccess) return e;
   }
-  if (e != hipSuccess) return e;
-  {
-    ProfScope prof(PROF_FFT_STRIDED, s);
-    e = ct_strided(p->N[1], 0, +1, work, work, p->ax[1].tw, Nh, (int64_t)p->N[1] * Nh, p->N[0], Nh, 1.0, f, XGeom{}, s);
-  }
-  if (e != hipSuccess) return e;
-  ProfScope prof(PROF_FFT_Z, s);
-  return ct_z_c2r(p->N[2], fout, work, out, p->ax[2].tw, npairs, out_scale, f, s);
+  return hipSuccess;
 }

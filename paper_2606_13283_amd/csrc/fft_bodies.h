@@ -1,0 +1,295 @@
+// Tile bodies of the compile-time FFT passes (fft_plans.h), shared by the
+// single-grid kernels (fft.hip) and the batched ones (fft_batch.hip): both run
+// the same code per tile, so a batched transform is bit-identical to a single one.
+#pragma once
+
+#include "fft.h"
+#include "fft_plans.h"
+
+namespace fftct {
+
+struct ColIn {  // column tile of a strided pass: element k of column `line`
+  const cplx* base;
+  int64_t es;
+  int nc;
+  __device__ cplx operator()(int line, int k) const { return line < nc ? base[(int64_t)k * es + line] : cplx{0.0, 0.0}; }
+};
+struct ColOut {
+  cplx* base;
+  int64_t es;
+  int nc;
+  double scale;
+  __device__ void operator()(int line, int k, cplx v) const {
+    if (line < nc) base[(int64_t)k * es + line] = cscale(v, scale);
+  }
+  __device__ void barrier_before() const {}
+  __device__ void barrier_after() const {}
+};
+
+struct ColOutLap {  // R2C_OUT_LAP
+  cplx* base;
+  int64_t es;
+  int nc;
+  double scale;
+  XGeom g;
+  int o, c0;
+  __device__ void operator()(int line, int k, cplx v) const {
+    if (line >= nc) return;
+    const double q2 = 39.478417604357434 * g.k2(k, o, c0 + line);  // (2 pi)^2 |k|^2
+    base[(int64_t)k * es + line] = cscale(v, -q2 * scale);
+  }
+  __device__ void barrier_before() const {}
+  __device__ void barrier_after() const {}
+};
+
+struct ColOutUH {  // R2C_OUT_UH
+  cplx* base;
+  const cplx* nhat_i;
+  int64_t es;
+  int nc;
+  double scale;
+  XGeom g;
+  int o, c0;
+  double* acc;
+  __device__ void operator()(int line, int k, cplx v) const {
+    if (line >= nc) return;
+    const int64_t at = (int64_t)k * es + line;
+    const cplx a = cscale(v, scale);
+    base[at] = a;
+    const double k2 = g.k2(k, o, c0 + line);
+    if (k2 > 0.0) {
+      const cplx d = csub(nhat_i[at], a);
+      *acc += g.weight(c0 + line) * (d.x * d.x + d.y * d.y) / (3.14159265358979323846 * k2);
+    }
+  }
+  __device__ void barrier_before() const {}
+  __device__ void barrier_after() const {}
+};
+
+struct ColInMix {  // C2R_IN_MIX: n_o^ = a + w (nhat_i - a); nhat_i <- n_o^; value n_o^/(pi k^2)
+  const cplx* a;
+  cplx* nhat_i;
+  int64_t es;
+  int nc;
+  double w;
+  XGeom g;
+  int o, c0;
+  __device__ cplx operator()(int line, int k) const {
+    if (line >= nc) return cplx{0.0, 0.0};
+    const int64_t at = (int64_t)k * es + line;
+    const cplx x = a[at];
+    const cplx no = cadd(x, cscale(csub(nhat_i[at], x), w));
+    nhat_i[at] = no;
+    const double k2 = g.k2(k, o, c0 + line);
+    return k2 > 0.0 ? cscale(no, 1.0 / (3.14159265358979323846 * k2)) : cplx{0.0, 0.0};
+  }
+};
+
+// One tile (block `bid` of the pass).  MODE 0: plain pass.  MODE 1/2/3: x pass
+// with R2C_OUT_LAP / R2C_OUT_UH / C2R_IN_MIX.
+template <int L, int TK, int S, int MODE>
+__device__ inline void strided_body(const StridedArgs& A, unsigned bid, cplx* lds, cplx* tw, double* sh) {
+  for (int i = threadIdx.x; i < L; i += ARCHE_BLOCK) tw[i] = A.tw[i];
+  __syncthreads();
+  const int o = (int)bid / A.nchunk;
+  const int c0 = ((int)bid - o * A.nchunk) * TK;
+  const int nc = (A.ncols - c0) < TK ? (A.ncols - c0) : TK;
+  cplx* base = A.data + (int64_t)o * A.os + c0;
+  const int64_t es = A.es;
+  if constexpr (MODE == 0) {
+    run<L, TK, ARCHE_BLOCK, true, S, 1>(ColIn{base, es, nc}, ColOut{base, es, nc, A.scale}, lds, tw, nc,
+                                         typename Plan<L>::R{});
+  } else if constexpr (MODE == 1) {
+    run<L, TK, ARCHE_BLOCK, true, S, 1>(ColIn{base, es, nc}, ColOutLap{base, es, nc, A.scale, A.g, o, c0}, lds, tw,
+                                         nc, typename Plan<L>::R{});
+  } else if constexpr (MODE == 2) {
+    double acc = 0.0;
+    run<L, TK, ARCHE_BLOCK, true, S, 1>(
+        ColIn{base, es, nc}, ColOutUH{base, A.f.nhat_i + (int64_t)o * A.os + c0, es, nc, A.scale, A.g, o, c0, &acc},
+        lds, tw, nc, typename Plan<L>::R{});
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) A.f.partials[bid] = acc;
+  } else {
+    const int64_t off = (int64_t)o * A.os + c0;
+    run<L, TK, ARCHE_BLOCK, true, S, 1>(ColInMix{A.src + off, A.f.nhat_i + off, es, nc, *A.f.w, A.g, o, c0},
+                                         ColOut{base, es, nc, A.scale}, lds, tw, nc, typename Plan<L>::R{});
+  }
+}
+template <int L, int TK>
+constexpr int strided_lds() {
+  return nstages(typename Plan<L>::R{}) > 1 ? lds_size<L, TK, true>() : 1;
+}
+
+struct PairIn {  // two real rows packed as one complex line
+  const double* src;
+  int L;
+  int nv;
+  double s;
+  __device__ cplx operator()(int line, int k) const {
+    if (line >= nv) return cplx{0.0, 0.0};
+    const double* r0 = src + (int64_t)line * 2 * L;
+    return cplx{r0[k] * s, r0[L + k] * s};
+  }
+};
+struct PairInSqrt {  // R2C_IN_SQRT
+  const double* src;
+  int L;
+  int nv;
+  double s;
+  __device__ cplx operator()(int line, int k) const {
+    if (line >= nv) return cplx{0.0, 0.0};
+    const double* r0 = src + (int64_t)line * 2 * L;
+    return cplx{sqrt(r0[k]) * s, sqrt(r0[L + k]) * s};
+  }
+};
+struct PairInMix {  // R2C_IN_MIX_SQRT: n_o = n_a + w (n_i - n_a); n_i <- n_o; sqrt(n_o)
+  const double* na;
+  double* ni;
+  int L;
+  int nv;
+  double s, w;
+  __device__ double one(int64_t at) const {
+    const double a = na[at];
+    const double o = a + w * (ni[at] - a);
+    ni[at] = o;
+    return sqrt(o) * s;
+  }
+  __device__ cplx operator()(int line, int k) const {
+    if (line >= nv) return cplx{0.0, 0.0};
+    const int64_t at = (int64_t)line * 2 * L + k;
+    return cplx{one(at), one(at + L)};
+  }
+};
+
+template <int L, int B, int FIN>
+__device__ inline void z_r2c_body(const ZArgs& A, unsigned bid, cplx* lds, cplx* tw) {
+  constexpr int Nh = L / 2 + 1;
+  for (int i = threadIdx.x; i < L; i += ARCHE_BLOCK) tw[i] = A.tw[i];
+  __syncthreads();
+  const double* in = (const double*)A.in;
+  const int64_t p0 = (int64_t)bid * B;
+  const int nb = (int)((A.npairs - p0) < B ? (A.npairs - p0) : B);
+  LdsIO<L, B, false> res{lds};
+  if constexpr (FIN == 0)
+    run<L, B, ARCHE_BLOCK, false, -1, 1>(PairIn{in + p0 * 2 * L, L, nb, A.in_scale}, res, lds, tw, nb,
+                                          typename Plan<L>::R{});
+  else if constexpr (FIN == 1)
+    run<L, B, ARCHE_BLOCK, false, -1, 1>(PairInSqrt{in + p0 * 2 * L, L, nb, A.in_scale}, res, lds, tw, nb,
+                                          typename Plan<L>::R{});
+  else
+    run<L, B, ARCHE_BLOCK, false, -1, 1>(PairInMix{in + p0 * 2 * L, A.f.n_i + p0 * 2 * L, L, nb, A.in_scale, *A.f.w},
+                                          res, lds, tw, nb, typename Plan<L>::R{});
+  cplx* dst = (cplx*)A.out + p0 * 2 * Nh;
+  for (int q = threadIdx.x; q < nb * 2 * Nh; q += ARCHE_BLOCK) {
+    const int l = q / (2 * Nh);
+    const int w = q - l * 2 * Nh;
+    const int r = w / Nh;
+    const int k = w - r * Nh;
+    const cplx zk = res(l, k);
+    const cplx zn = res(l, k == 0 ? 0 : L - k);
+    cplx v;
+    if (r == 0)
+      v = cplx{0.5 * (zk.x + zn.x), 0.5 * (zk.y - zn.y)};
+    else
+      v = cplx{0.5 * (zk.y + zn.y), -0.5 * (zk.x - zn.x)};
+    dst[q] = cscale(v, A.out_scale);
+  }
+}
+template <int L, int B>
+constexpr int z_r2c_lds() {
+  return lds_size<L, B, false>();
+}
+
+struct HermIn {  // Z_k = X_k + i Y_k from the half spectra of two real rows
+  const cplx* src;
+  int L, Nh, nv;
+  __device__ cplx operator()(int line, int k) const {
+    if (line >= nv) return cplx{0.0, 0.0};
+    const cplx* X = src + (int64_t)line * 2 * Nh;
+    const cplx* Y = X + Nh;
+    cplx x, y;
+    if (k == 0 || 2 * k == L) {
+      x = cplx{X[k].x, 0.0};
+      y = cplx{Y[k].x, 0.0};
+    } else if (2 * k < L) {
+      x = X[k];
+      y = Y[k];
+    } else {
+      x = cconj(X[L - k]);
+      y = cconj(Y[L - k]);
+    }
+    return cplx{x.x - y.y, x.y + y.x};
+  }
+};
+struct PairOut {
+  double* dst;
+  int L, nv;
+  double scale;
+  __device__ void operator()(int line, int k, cplx v) const {
+    if (line >= nv) return;
+    double* r0 = dst + (int64_t)line * 2 * L;
+    r0[k] = v.x * scale;
+    r0[L + k] = v.y * scale;
+  }
+  __device__ void barrier_before() const {}
+  __device__ void barrier_after() const {}
+};
+
+struct PairOutUvw {  // C2R_OUT_UVW: accumulate (v_vW[n_i] - v_vW[n_a]) (n_i - n_a), no store
+  const double* ni;
+  const double* lapi;
+  const double* na;
+  int L, nv;
+  double scale, hl;  // hl = lambda/2
+  double* acc;
+  __device__ void one(int64_t at, double lap) const {
+    const double a = ni[at], b = na[at];
+    const double vi = -hl * lapi[at] / sqrt(a);
+    const double va = -hl * lap / sqrt(b);
+    *acc += (vi - va) * (a - b);
+  }
+  __device__ void operator()(int line, int k, cplx v) const {
+    if (line >= nv) return;
+    const int64_t at = (int64_t)line * 2 * L + k;
+    one(at, v.x * scale);
+    one(at + L, v.y * scale);
+  }
+  __device__ void barrier_before() const {}
+  __device__ void barrier_after() const {}
+};
+
+template <int L, int B, int FOUT>
+__device__ inline void z_c2r_body(const ZArgs& A, unsigned bid, cplx* lds, cplx* tw, double* sh) {
+  constexpr int Nh = L / 2 + 1;
+  for (int i = threadIdx.x; i < L; i += ARCHE_BLOCK) tw[i] = A.tw[i];
+  __syncthreads();
+  const cplx* in = (const cplx*)A.in;
+  const int64_t p0 = (int64_t)bid * B;
+  const int nb = (int)((A.npairs - p0) < B ? (A.npairs - p0) : B);
+  if constexpr (FOUT == 0) {
+    run<L, B, ARCHE_BLOCK, false, +1, 1>(HermIn{in + p0 * 2 * Nh, L, Nh, nb},
+                                          PairOut{(double*)A.out + p0 * 2 * L, L, nb, A.out_scale}, lds, tw, nb,
+                                          typename Plan<L>::R{});
+  } else {
+    double acc = 0.0;
+    const int64_t off = p0 * 2 * L;
+    run<L, B, ARCHE_BLOCK, false, +1, 1>(
+        HermIn{in + p0 * 2 * Nh, L, Nh, nb},
+        PairOutUvw{A.f.n_i + off, A.f.lap_i + off, A.f.n_a + off, L, nb, A.out_scale, 0.5 * A.f.lam, &acc}, lds, tw,
+        nb, typename Plan<L>::R{});
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) A.f.partials[bid] = acc;
+  }
+}
+template <int L, int B>
+constexpr int z_c2r_lds() {
+  return nstages(typename Plan<L>::R{}) > 1 ? lds_size<L, B, false>() : 1;
+}
+
+constexpr int CT_TK = 16;
+template <int L>
+constexpr int ct_rows() {
+  return L >= 96 ? 16 : 32;
+}
+
+}  // namespace fftct

@@ -120,9 +120,30 @@ arche_status validate(const arche_params* p, std::string& msg) {
   return ARCHE_OK;
 }
 
-// SCF loop: one queued iteration ahead of the convergence poll
+// SCF state -> result fields and the context's error text
+arche_status collect_state(arche_ctx* c, arche_result* out) {
+  ScfState st;
+  CK(hipMemcpyAsync(&st, c->state, sizeof(ScfState), hipMemcpyDeviceToHost, c->stream));
+  CK(hipStreamSynchronize(c->stream));
+  std::memset(out, 0, sizeof(*out));
+  out->mu = st.mu;
+  out->residual = st.res;
+  out->w_last = st.w;
+  out->scf_iters = st.iter;
+  out->newton_iters = st.newton_total;
+  out->converged = st.done && !st.err && st.res < c->p.scf_tol;
+  c->converged = out->converged;
+  if (st.err) {
+    c->err = st.mu_fail ? "chemical-potential search did not converge" : "non-finite value or barrier time-out in SCF";
+  } else if (!out->converged) {
+    c->err = "SCF did not reach scf_tol within scf_max_iter";
+  }
+  return ARCHE_OK;
+}
+
+// SCF loop: one queued iteration ahead of the convergence poll.  The state was
+// reset by begin_solve; the last iteration raises done by itself.
 arche_status run_scf(arche_ctx* c, arche_result* out) {
-  CK(scf_reset_state(c, NAN));
   hipEvent_t ev[2];
   CK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
   CK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
@@ -145,23 +166,7 @@ arche_status run_scf(arche_ctx* c, arche_result* out) {
   }
   (void)hipEventDestroy(ev[0]);
   (void)hipEventDestroy(ev[1]);
-  ScfState st;
-  CK(hipMemcpyAsync(&st, c->state, sizeof(ScfState), hipMemcpyDeviceToHost, c->stream));
-  CK(hipStreamSynchronize(c->stream));
-  std::memset(out, 0, sizeof(*out));
-  out->mu = st.mu;
-  out->residual = st.res;
-  out->w_last = st.w;
-  out->scf_iters = st.iter;
-  out->newton_iters = st.newton_total;
-  out->converged = st.done && !st.err && st.res < c->p.scf_tol;
-  c->converged = out->converged;
-  if (st.err) {
-    c->err = st.mu_fail ? "chemical-potential search did not converge" : "non-finite value or barrier time-out in SCF";
-  } else if (!out->converged) {
-    c->err = "SCF did not reach scf_tol within scf_max_iter";
-  }
-  return ARCHE_OK;
+  return collect_state(c, out);
 }
 
 arche_status evaluate(arche_ctx* c, arche_result* out) {
@@ -215,8 +220,8 @@ struct ProfInstall {
   }
 };
 
-arche_status do_solve(arche_ctx* c, const double* pos_host, arche_result* out, int init) {
-  ProfInstall pi(c);
+// positions, structure factor and ionic field, initial density, fresh SCF state
+arche_status begin_solve(arche_ctx* c, const double* pos_host, int init, int* fallback) {
   const int n = c->n_atoms;
   for (int q = 0; q < 3 * n; ++q)
     if (!std::isfinite(pos_host[q])) return set_err(c, ARCHE_EINVAL, "non-finite position");
@@ -225,18 +230,22 @@ arche_status do_solve(arche_ctx* c, const double* pos_host, arche_result* out, i
   c->forces_ready = false;
   CK(hipMemcpyAsync(c->pos, c->h_pos.data(), 3 * n * sizeof(double), hipMemcpyHostToDevice, c->stream));
   CK(ionic_structure(c));
-  int fallback = 0;
+  *fallback = 0;
   if (init == ARCHE_INIT_ONE_CENTER && c->have_prev) {
-    CK(scf_initial_one_center(c, &fallback));
+    CK(scf_initial_one_center(c, fallback));
   } else if (init == ARCHE_INIT_KEEP && c->solved) {
     CK(scf_prepare_input(c));
   } else {
     CK(scf_initial_uniform(c));
   }
-  arche_status s = run_scf(c, out);
-  if (s != ARCHE_OK) return s;
+  CK(scf_reset_state(c, NAN));
+  return ARCHE_OK;
+}
+
+// energies and pressure at the converged state; keeps what the next guess needs
+arche_status finish_solve(arche_ctx* c, arche_result* out, int fallback) {
   out->used_fallback = fallback;
-  s = evaluate(c, out);
+  arche_status s = evaluate(c, out);
   if (s != ARCHE_OK) return s;
   // keep the converged spectrum and the charge structure factor for the next one-center guess
   const size_t hb = c->g.nh * sizeof(cplx);
@@ -248,6 +257,16 @@ arche_status do_solve(arche_ctx* c, const double* pos_host, arche_result* out, i
   c->solved = true;
   c->last = *out;
   return out->converged ? ARCHE_OK : ARCHE_ENOCONV;
+}
+
+arche_status do_solve(arche_ctx* c, const double* pos_host, arche_result* out, int init) {
+  ProfInstall pi(c);
+  int fallback = 0;
+  arche_status s = begin_solve(c, pos_host, init, &fallback);
+  if (s != ARCHE_OK) return s;
+  s = run_scf(c, out);
+  if (s != ARCHE_OK) return s;
+  return finish_solve(c, out, fallback);
 }
 
 arche_status do_forces(arche_ctx* c) {
@@ -264,6 +283,14 @@ arche_status do_forces(arche_ctx* c) {
 }
 
 }  // namespace
+
+arche_status solve_begin(arche_ctx* c, const double* pos_host, int init, int* fallback) {
+  return begin_solve(c, pos_host, init, fallback);
+}
+arche_status solve_collect(arche_ctx* c, arche_result* out) { return collect_state(c, out); }
+arche_status solve_finish(arche_ctx* c, arche_result* out, int fallback) { return finish_solve(c, out, fallback); }
+arche_status solve_forces(arche_ctx* c) { return do_forces(c); }
+arche_status ctx_error(arche_ctx* c, arche_status s, const std::string& m) { return set_err(c, s, m); }
 
 extern "C" {
 
@@ -330,6 +357,8 @@ arche_status arche_scf_init(const arche_params* p, void* hip_stream, arche_ctx**
     c->stream = (hipStream_t)hip_stream;
   } else if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
     return fail_init(ARCHE_EHIP, "hipStreamCreate failed");
+  } else {
+    c->own_stream = true;
   }
   int dev_attr = 0;
   (void)hipDeviceGetAttribute(&dev_attr, hipDeviceAttributeCooperativeLaunch, c->device);
@@ -494,6 +523,7 @@ void arche_scf_free(arche_ctx* c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   free_all(c);
+  if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
 

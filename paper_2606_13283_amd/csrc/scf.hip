@@ -17,27 +17,6 @@ __device__ inline void put_slot(double* part, int slot, unsigned nb, double v) {
   if (threadIdx.x == 0) coherent_store(part + (size_t)slot * nb + blockIdx.x, v);  // read by grid_allreduce
 }
 
-struct ActiveArgs {
-  const double* Vie;
-  const double* VH;
-  const double* lap_i;
-  const double* n_i;
-  double* Vi;
-  double* n_a;
-  ScfState* st;
-  double* part;     // [13][nchunk] chunk partials
-  double* res;      // reduced scalars
-  unsigned* flags;  // [G] arrival flags of the group, then the go word
-  int* err;
-  const FdTables* fdt;
-  int64_t ng, nchunk;
-  double dv, kT, cn, Ne, lam;
-  int xc;
-  double eta0, tol;
-  int mixing, warmup;
-  double trust;
-  int max_newton;
-};
 
 // The grid is cut into chunks of SCF_CHUNK consecutive points; thread t of the
 // block that owns a chunk handles points t + ARCHE_BLOCK*q, q < PPT.  Every
@@ -221,7 +200,7 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
     if (!found) st->mu_fail = 1;
     const bool bad = !(res == res) || !found || *a.err;
     if (bad) st->err = 1;
-    st->done = (res < a.tol) || bad;
+    st->done = (res < a.tol) || bad || (t + 1 >= a.max_iter);
   }
 }
 
@@ -305,30 +284,37 @@ k_uh_partial(const ScfState* st, const cplx* nhat_i, const cplx* nhat_a, GridInf
 }
 
 // Mixing weight (Sec. 2.5.2): w = U/(U+K) with U = U_H + U_xc + U_vW once the More
-// weight is on, else w_fixed; clamped to [0, 0.995].
-__global__ void __launch_bounds__(ARCHE_BLOCK)
-k_mix_weight(ScfState* st, const double* part_h, int nbh, const double* part_v, int nbv, int use_vw,
-             double vol, double dv, double w_fixed) {
-  __shared__ double sh[ARCHE_BLOCK / 64];
+// weight is on, else w_fixed; clamped to [0, 0.995].  One block per system.
+__device__ inline void mix_weight_body(const MixWeightArgs& m, double* sh) {
+  ScfState* st = m.st;
   if (st->done) return;
   double a = 0.0, b = 0.0;
-  for (int t = threadIdx.x; t < nbh; t += blockDim.x) a += part_h[t];
+  for (int t = threadIdx.x; t < m.nbh; t += blockDim.x) a += m.part_h[t];
   a = block_sum(a, sh);
-  if (use_vw && st->more_on)
-    for (int t = threadIdx.x; t < nbv; t += blockDim.x) b += part_v[t];
+  if (m.use_vw && st->more_on)
+    for (int t = threadIdx.x; t < m.nbv; t += blockDim.x) b += m.part_v[t];
   b = block_sum(b, sh);
   if (threadIdx.x == 0) {
-    st->UH = a / vol;
-    st->Uvw = (use_vw && st->more_on) ? dv * b : 0.0;
-    double w = w_fixed;
+    st->UH = a / m.vol;
+    st->Uvw = (m.use_vw && st->more_on) ? m.dv * b : 0.0;
+    double w = m.w_fixed;
     if (st->more_on) {
       const double U = st->UH + st->Uxc + st->Uvw;
       w = U / (U + st->K);
       w = fmin(fmax(w, 0.0), 0.995);
-      if (!(w == w)) w = w_fixed;
+      if (!(w == w)) w = m.w_fixed;
     }
     st->w = w;
   }
+}
+__global__ void __launch_bounds__(ARCHE_BLOCK) k_mix_weight(MixWeightArgs m) {
+  __shared__ double sh[ARCHE_BLOCK / 64];
+  mix_weight_body(m, sh);
+}
+__global__ void __launch_bounds__(ARCHE_BLOCK) k_mix_weight_batch(const MixWeightArgs* __restrict__ jobs) {
+  __shared__ double sh[ARCHE_BLOCK / 64];
+  const MixWeightArgs m = jobs[blockIdx.x];
+  mix_weight_body(m, sh);
 }
 
 // n^_o = n^_a + w (n^_i - n^_a) -> nhat_i;  tmp = n^_o / (pi k^2) (0 at k = 0)
@@ -348,17 +334,30 @@ k_spec_mix(const ScfState* st, cplx* nhat_i, const cplx* nhat_a, cplx* tmp, Grid
   }
 }
 
-// n_o = n_a + w (n_i - n_a) -> n_i;  sq = sqrt(n_o)
-__global__ void __launch_bounds__(ARCHE_BLOCK)
-k_real_mix(const ScfState* st, double* n_i, const double* n_a, double* sq, int64_t ng) {
-  if (st->done) return;
-  const double w = st->w;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ng; i += (int64_t)gridDim.x * blockDim.x) {
-    const double na = n_a[i];
-    const double no = na + w * (n_i[i] - na);
-    n_i[i] = no;
-    sq[i] = sqrt(no);
+// n_o = n_a + w (n_i - n_a) -> n_i;  sq = sqrt(n_o)   (block bid of nb)
+__device__ inline void real_mix_body(const RealMixArgs& r, unsigned bid, unsigned nb) {
+  if (r.st->done) return;
+  const double w = r.st->w;
+  for (int64_t i = (int64_t)bid * blockDim.x + threadIdx.x; i < r.ng; i += (int64_t)nb * blockDim.x) {
+    const double na = r.n_a[i];
+    const double no = na + w * (r.n_i[i] - na);
+    r.n_i[i] = no;
+    r.sq[i] = sqrt(no);
   }
+}
+__global__ void __launch_bounds__(ARCHE_BLOCK) k_real_mix(RealMixArgs r) { real_mix_body(r, blockIdx.x, gridDim.x); }
+__global__ void __launch_bounds__(ARCHE_BLOCK)
+k_real_mix_batch(const RealMixArgs* __restrict__ jobs, const int* __restrict__ bbeg, int njobs) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (bbeg[mid] <= (int)blockIdx.x)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const RealMixArgs r = jobs[lo];
+  real_mix_body(r, blockIdx.x - (unsigned)bbeg[lo], (unsigned)(bbeg[lo + 1] - bbeg[lo]));
 }
 
 __global__ void __launch_bounds__(ARCHE_BLOCK)
@@ -575,52 +574,10 @@ int scf_coop_blocks(int64_t ng) {
   return (int)std::max<int64_t>(b, 1);
 }
 
-// The rest of an SCF iteration with the spectral and pointwise steps fused into
-// the FFT passes (fft.h): R2C(n_a) also sums U_H; [More + vW: R2C(sqrt n_a) with
-// the Laplacian on store, C2R that sums U_vW instead of storing]; the weight;
-// C2R of n_o^/(pi k^2) that forms n_o^ from n^_a and n^_i on load; R2C of
-// sqrt(n_o) that forms n_o on load, Laplacian on store, C2R -> lap sqrt(n_o).
-static hipError_t scf_iteration_rest_fused(arche_ctx* c, bool vw, bool more) {
+static ActiveArgs active_args(const arche_ctx* c) {
   const GridInfo& g = c->g;
   const arche_params& p = c->p;
-  const int nbh = fft_x_blocks(&c->plan);
-  const int nbv = fft_z_blocks(&c->plan);
-  double* part_h = c->partials + scf_part_offset(c);
-  double* part_v = part_h + nbh;
-  FftFuse f{};
-  f.w = &c->state->w;
-  f.n_i = c->n_i;
-  f.n_a = c->n_a;
-  f.lap_i = c->lap_i;
-  f.nhat_i = c->nhat_i;
-  f.lam = p.lambda_vw;
-  f.L[0] = g.L[0];
-  f.L[1] = g.L[1];
-  f.L[2] = g.L[2];
-  f.partials = part_h;
-  HIP_TRY(fft_r2c_fused(&c->plan, c->n_a, c->nhat_a, 1.0, g.dv, FUSE_NONE, R2C_OUT_UH, f, c->stream));
-  if (more && vw) {
-    HIP_TRY(fft_r2c_fused(&c->plan, c->n_a, c->ctmp, 1.0, g.dv, R2C_IN_SQRT, R2C_OUT_LAP, f, c->stream));
-    f.partials = part_v;
-    HIP_TRY(fft_c2r_fused(&c->plan, c->ctmp, c->ctmp, nullptr, 1.0 / g.vol, FUSE_NONE, C2R_OUT_UVW, f, c->stream));
-  }
-  hipLaunchKernelGGL(k_mix_weight, dim3(1), dim3(ARCHE_BLOCK), 0, c->stream, c->state, part_h, nbh, part_v, nbv,
-                     (int)(more && vw), g.vol, g.dv, p.w_fixed);
-  HIP_TRY(hipGetLastError());
-  HIP_TRY(fft_c2r_fused(&c->plan, c->nhat_a, c->ctmp, c->VH, 1.0 / g.vol, C2R_IN_MIX, FUSE_NONE, f, c->stream));
-  if (vw) {
-    HIP_TRY(fft_r2c_fused(&c->plan, c->n_a, c->ctmp, 1.0, g.dv, R2C_IN_MIX_SQRT, R2C_OUT_LAP, f, c->stream));
-    return fft_c2r(&c->plan, c->ctmp, c->lap_i, 1.0 / g.vol, c->stream);
-  }
-  hipLaunchKernelGGL(k_real_mix, dim3(grid_for(g.ng)), dim3(ARCHE_BLOCK), 0, c->stream, (const ScfState*)c->state,
-                     c->n_i, c->n_a, c->rtmp, g.ng);
-  return hipGetLastError();
-}
-
-hipError_t scf_iteration(arche_ctx* c) {
-  const GridInfo& g = c->g;
-  const arche_params& p = c->p;
-  ActiveArgs a;
+  ActiveArgs a{};
   a.Vie = c->Vie;
   a.VH = c->VH;
   a.lap_i = c->lap_i;
@@ -647,16 +604,105 @@ hipError_t scf_iteration(arche_ctx* c) {
   a.warmup = p.more_warmup;
   a.trust = p.more_trust;
   a.max_newton = 200;  // < 250 all-reduces per launch keeps the epochs of launches disjoint
-  void* args[] = {&a};
-  const bool cache = a.nchunk <= c->coop_blocks;
-  {
-    ProfScope prof(PROF_SCF_ACTIVE, c->stream);
-    HIP_TRY(hipLaunchCooperativeKernel(cache ? (const void*)k_scf_active<true> : (const void*)k_scf_active<false>,
-                                       dim3(c->coop_blocks), dim3(ARCHE_BLOCK), args, 0, c->stream));
+  a.max_iter = p.scf_max_iter;
+  return a;
+}
+
+static void push_fft(std::vector<IterStep>& v, int slot, const FftPass* ps) {
+  for (int i = 0; i < 3; ++i) {
+    IterStep st{};
+    st.slot = slot + i;
+    st.kind = STEP_FFT;
+    st.fft = ps[i];
+    st.nblocks = ps[i].nblocks;
+    v.push_back(st);
   }
+}
+
+// The rest of an SCF iteration with the spectral and pointwise steps fused into
+// the FFT passes (fft.h): R2C(n_a) also sums U_H; [More + vW: R2C(sqrt n_a) with
+// the Laplacian on store, C2R that sums U_vW instead of storing]; the weight;
+// C2R of n_o^/(pi k^2) that forms n_o^ from n^_a and n^_i on load; R2C of
+// sqrt(n_o) that forms n_o on load, Laplacian on store, C2R -> lap sqrt(n_o).
+// Every pass stops once the state's done flag is raised.
+void scf_build_iteration(arche_ctx* c) {
+  if (c->iter_built) return;
+  c->active = active_args(c);
+  c->steps.clear();
+  c->fused = fft_fusable(&c->plan);
+  c->iter_built = true;
+  if (!c->fused) return;
+  const GridInfo& g = c->g;
+  const arche_params& p = c->p;
   const bool vw = p.lambda_vw != 0.0;
   const bool more = p.mixing == ARCHE_MIX_MORE;
-  if (fft_fusable(&c->plan)) return scf_iteration_rest_fused(c, vw, more);
+  const int nbh = fft_x_blocks(&c->plan);
+  const int nbv = fft_z_blocks(&c->plan);
+  double* part_h = c->partials + scf_part_offset(c);
+  double* part_v = part_h + nbh;
+  FftFuse f{};
+  f.w = &c->state->w;
+  f.n_i = c->n_i;
+  f.n_a = c->n_a;
+  f.lap_i = c->lap_i;
+  f.nhat_i = c->nhat_i;
+  f.lam = p.lambda_vw;
+  f.L[0] = g.L[0];
+  f.L[1] = g.L[1];
+  f.L[2] = g.L[2];
+  f.partials = part_h;
+  f.stop = &c->state->done;
+  FftPass ps[3];
+  fft_r2c_passes(&c->plan, c->n_a, c->nhat_a, 1.0, g.dv, FUSE_NONE, R2C_OUT_UH, f, ps);
+  push_fft(c->steps, SLOT_NHAT_A, ps);
+  if (more && vw) {
+    fft_r2c_passes(&c->plan, c->n_a, c->ctmp, 1.0, g.dv, R2C_IN_SQRT, R2C_OUT_LAP, f, ps);
+    push_fft(c->steps, SLOT_LAP_A, ps);
+    FftFuse fv = f;
+    fv.partials = part_v;
+    fft_c2r_passes(&c->plan, c->ctmp, c->ctmp, nullptr, 1.0 / g.vol, FUSE_NONE, C2R_OUT_UVW, fv, ps);
+    push_fft(c->steps, SLOT_UVW, ps);
+  }
+  IterStep w{};
+  w.slot = SLOT_WEIGHT;
+  w.kind = STEP_WEIGHT;
+  w.nblocks = 1;
+  w.mw = MixWeightArgs{c->state, part_h, nbh, part_v, nbv, (int)(more && vw), g.vol, g.dv, p.w_fixed};
+  c->steps.push_back(w);
+  fft_c2r_passes(&c->plan, c->nhat_a, c->ctmp, c->VH, 1.0 / g.vol, C2R_IN_MIX, FUSE_NONE, f, ps);
+  push_fft(c->steps, SLOT_HARTREE, ps);
+  if (vw) {
+    fft_r2c_passes(&c->plan, c->n_a, c->ctmp, 1.0, g.dv, R2C_IN_MIX_SQRT, R2C_OUT_LAP, f, ps);
+    push_fft(c->steps, SLOT_SQRT_O, ps);
+    fft_c2r_passes(&c->plan, c->ctmp, c->ctmp, c->lap_i, 1.0 / g.vol, FUSE_NONE, FUSE_NONE, f, ps);
+    push_fft(c->steps, SLOT_LAP_O, ps);
+  } else {
+    IterStep r{};
+    r.slot = SLOT_REAL_MIX;
+    r.kind = STEP_REAL_MIX;
+    r.nblocks = scf_real_mix_blocks(g.ng);
+    r.rm = RealMixArgs{c->state, c->n_i, c->n_a, c->rtmp, g.ng};
+    c->steps.push_back(r);
+  }
+}
+
+unsigned scf_real_mix_blocks(int64_t ng) { return grid_for(ng); }
+
+hipError_t scf_step_launch(const IterStep& st, hipStream_t s) {
+  if (st.kind == STEP_FFT) return fft_pass_launch(st.fft, s);
+  if (st.kind == STEP_WEIGHT)
+    hipLaunchKernelGGL(k_mix_weight, dim3(1), dim3(ARCHE_BLOCK), 0, s, st.mw);
+  else
+    hipLaunchKernelGGL(k_real_mix, dim3(st.nblocks), dim3(ARCHE_BLOCK), 0, s, st.rm);
+  return hipGetLastError();
+}
+
+// the unfused sequence, for grids without compile-time FFT plans
+static hipError_t scf_iteration_rest_plain(arche_ctx* c) {
+  const GridInfo& g = c->g;
+  const arche_params& p = c->p;
+  const bool vw = p.lambda_vw != 0.0;
+  const bool more = p.mixing == ARCHE_MIX_MORE;
   // n^_a
   HIP_TRY(fft_r2c(&c->plan, c->n_a, c->nhat_a, 1.0, g.dv, c->stream));
   const int nbr = red_blocks(g.ng);
@@ -679,15 +725,15 @@ hipError_t scf_iteration(arche_ctx* c) {
   hipLaunchKernelGGL(k_uh_partial, dim3(nbh), dim3(ARCHE_BLOCK), 0, c->stream, (const ScfState*)c->state, c->nhat_i,
                      c->nhat_a, g, part_h);
   HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_mix_weight, dim3(1), dim3(ARCHE_BLOCK), 0, c->stream, c->state, part_h, nbh, part_v, nbr,
-                     (int)(more && vw), g.vol, g.dv, p.w_fixed);
+  const MixWeightArgs mw{c->state, part_h, nbh, part_v, nbr, (int)(more && vw), g.vol, g.dv, p.w_fixed};
+  hipLaunchKernelGGL(k_mix_weight, dim3(1), dim3(ARCHE_BLOCK), 0, c->stream, mw);
   HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_spec_mix, dim3(grid_for(g.nh)), dim3(ARCHE_BLOCK), 0, c->stream, (const ScfState*)c->state,
                      c->nhat_i, c->nhat_a, c->ctmp, g);
   HIP_TRY(hipGetLastError());
   HIP_TRY(fft_c2r(&c->plan, c->ctmp, c->VH, 1.0 / g.vol, c->stream));
-  hipLaunchKernelGGL(k_real_mix, dim3(grid_for(g.ng)), dim3(ARCHE_BLOCK), 0, c->stream, (const ScfState*)c->state,
-                     c->n_i, c->n_a, c->rtmp, g.ng);
+  const RealMixArgs rm{c->state, c->n_i, c->n_a, c->rtmp, g.ng};
+  hipLaunchKernelGGL(k_real_mix, dim3(grid_for(g.ng)), dim3(ARCHE_BLOCK), 0, c->stream, rm);
   HIP_TRY(hipGetLastError());
   if (vw) {
     HIP_TRY(fft_r2c(&c->plan, c->rtmp, c->ctmp, 1.0, g.dv, c->stream));
@@ -696,6 +742,51 @@ hipError_t scf_iteration(arche_ctx* c) {
     HIP_TRY(fft_c2r(&c->plan, c->ctmp, c->lap_i, 1.0 / g.vol, c->stream));
   }
   return hipSuccess;
+}
+
+hipError_t scf_iteration(arche_ctx* c) {
+  scf_build_iteration(c);
+  void* args[] = {&c->active};
+  const bool cache = c->active.nchunk <= c->coop_blocks;
+  {
+    ProfScope prof(PROF_SCF_ACTIVE, c->stream);
+    HIP_TRY(hipLaunchCooperativeKernel(cache ? (const void*)k_scf_active<true> : (const void*)k_scf_active<false>,
+                                       dim3(c->coop_blocks), dim3(ARCHE_BLOCK), args, 0, c->stream));
+  }
+  if (!c->fused) return scf_iteration_rest_plain(c);
+  for (const IterStep& st : c->steps) HIP_TRY(scf_step_launch(st, c->stream));
+  return hipSuccess;
+}
+
+int scf_batch_capacity() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_scf_active_batch, ARCHE_BLOCK, 0) != hipSuccess)
+    return 0;
+  return per_cu * cus;
+}
+
+hipError_t scf_active_batch_launch(const ActiveArgs* args, const int* group_begin, int nsys, int nblocks,
+                                   hipStream_t s) {
+  void* kargs[] = {&args, &group_begin, &nsys};
+  ProfScope prof(PROF_SCF_ACTIVE, s);
+  return hipLaunchCooperativeKernel((const void*)k_scf_active_batch, dim3(nblocks), dim3(ARCHE_BLOCK), kargs, 0, s);
+}
+
+hipError_t scf_weight_batch_launch(const MixWeightArgs* jobs, int njobs, hipStream_t s) {
+  if (njobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mix_weight_batch, dim3(njobs), dim3(ARCHE_BLOCK), 0, s, jobs);
+  return hipGetLastError();
+}
+
+hipError_t scf_real_mix_batch_launch(const RealMixArgs* jobs, const int* bbeg, int njobs, unsigned nblocks,
+                                     hipStream_t s) {
+  if (njobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_real_mix_batch, dim3(nblocks), dim3(ARCHE_BLOCK), 0, s, jobs, bbeg, njobs);
+  return hipGetLastError();
 }
 
 // out: 0 F_TF, 1 K_e, 2 F_xc, 3 P_xc, 4 int n V^ie, 5 int n, 6 E_H, 7 F_vW, 8 P_TF
