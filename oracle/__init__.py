@@ -16,6 +16,8 @@ Modules
   scf       SCF loop: Newton on mu, More mixing, initial densities (Sec. 2.5)
   thermo    free energy and pressure at the converged density (Sec. 2.6)
   md        Verlet step (Sec. 2.1)
+  unet      the learned initial-density network (an addition to Sec. 2.5.1's
+            guesses): forward pass, loss and gradients in FP64
 
 Functions whose result no independent pin checks say "parity unpinned" in
 their docstring.
