@@ -44,7 +44,8 @@ typedef enum {
 enum {
   ARCHE_INIT_UNIFORM = 0,    /* n_0 = N_e / |Omega| */
   ARCHE_INIT_ONE_CENTER = 1, /* superposition guess from the previous converged step; uniform if none */
-  ARCHE_INIT_KEEP = 2        /* the context's current density (e.g. from arche_set_density) */
+  ARCHE_INIT_KEEP = 2,       /* the context's current density (e.g. from arche_set_density) */
+  ARCHE_INIT_LEARNED = 3     /* the learned proposal of arche_net.h; one-center if none */
 };
 /* density mixing (Sec. 2.5.2) */
 enum { ARCHE_MIX_FIXED = 0, ARCHE_MIX_MORE = 1 };
@@ -102,7 +103,7 @@ typedef struct {
   double w_last;                  /* last mixing weight */
   int32_t scf_iters;
   int32_t newton_iters;           /* total Newton passes of the mu search */
-  int32_t used_fallback;          /* one-center guess replaced by the uniform one */
+  int32_t used_fallback;          /* the requested guess was replaced (one-center by uniform, learned by one-center) */
   int32_t converged;
 } arche_result;
 

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libarche.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENOCONV, ESTATE = 0, -1, -2, -3, -4, -5
-INIT_UNIFORM, INIT_ONE_CENTER, INIT_KEEP = 0, 1, 2
+INIT_UNIFORM, INIT_ONE_CENTER, INIT_KEEP, INIT_LEARNED = 0, 1, 2, 3
 MIX_FIXED, MIX_MORE = 0, 1
 XC_NONE, XC_LDA = 0, 1
 TERM_NAMES = ("F_TF", "K_e", "F_vW", "E_H", "F_xc", "E_ie", "U_ii", "U_pp", "U_pm", "U_je", "alpha")
@@ -122,6 +122,32 @@ def load(path: str = LIB_PATH):
     L.arche_scf_solve_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(Params), ctypes.POINTER(_dp),
                                         ctypes.POINTER(Result), vp]
     L.arche_scf_solve_batch.restype = st
+    L.arche_net_param_count.argtypes = []
+    L.arche_net_param_count.restype = ctypes.c_int64
+    L.arche_net_create.argtypes = [_ip, vp, ctypes.POINTER(vp)]
+    L.arche_net_create.restype = st
+    _fp = ctypes.POINTER(ctypes.c_float)
+    for nm in ("arche_net_set_params", "arche_net_get_params", "arche_net_get_grads"):
+        getattr(L, nm).argtypes = [vp, _fp, ctypes.c_int64]
+        getattr(L, nm).restype = st
+    L.arche_net_forward.argtypes = [vp, vp, vp, ctypes.c_double, vp]
+    L.arche_net_forward.restype = st
+    L.arche_net_propose.argtypes = [vp, vp, vp, ctypes.c_double, vp]
+    L.arche_net_propose.restype = st
+    L.arche_net_loss_grad.argtypes = [vp, vp, vp, vp, ctypes.c_double, _dp]
+    L.arche_net_loss_grad.restype = st
+    L.arche_net_adam_step.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+    L.arche_net_adam_step.restype = st
+    L.arche_net_debug_get.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, _fp]
+    L.arche_net_debug_get.restype = st
+    L.arche_net_sync.argtypes = [vp]
+    L.arche_net_sync.restype = st
+    L.arche_net_last_error.argtypes = [vp]
+    L.arche_net_last_error.restype = ctypes.c_char_p
+    L.arche_net_free.argtypes = [vp]
+    L.arche_net_free.restype = None
+    L.arche_set_init_net.argtypes = [vp, vp]
+    L.arche_set_init_net.restype = st
     L.arche_k_fft_r2c.argtypes = [_ip, vp, vp, vp]
     L.arche_k_fft_r2c.restype = st
     L.arche_k_fft_c2r.argtypes = [_ip, vp, vp, vp]
@@ -242,6 +268,11 @@ class Context:
         n = _f64(n, self.grid)
         self._check(self._L.arche_set_density(self._h, _ptr(n), 0))
 
+    def set_init_net(self, net):
+        """Use `net` (a Net on the same grid, or None) for INIT_LEARNED solves."""
+        self._net = net
+        self._check(self._L.arche_set_init_net(self._h, net._h if net is not None else None))
+
     def reset_history(self):
         self._check(self._L.arche_reset_history(self._h))
 
@@ -359,6 +390,83 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None):
             self._L.arche_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Net:
+    """The learned initial-density U-Net (arche_net_*).  Fields are FP64 torch
+    tensors on the HIP device (torch supplies the memory only); parameters are
+    FP32 numpy arrays in the documented order."""
+
+    def __init__(self, grid, stream=None):
+        L = load()
+        self._L = L
+        self.grid = tuple(int(g) for g in grid)
+        g = (ctypes.c_int32 * 3)(*self.grid)
+        h = ctypes.c_void_p()
+        s = L.arche_net_create(g, ctypes.c_void_p(stream) if stream else None, ctypes.byref(h))
+        if s != OK:
+            raise ArcheError(s, "arche_net_create failed (grid edges multiples of 8, product of 16384)")
+        self._h = h
+        self.n_params = int(L.arche_net_param_count())
+
+    def _check(self, s):
+        if s != OK:
+            raise ArcheError(s, self._L.arche_net_last_error(self._h).decode())
+
+    @staticmethod
+    def _dev(t):
+        assert t.is_cuda and t.dtype.is_floating_point and t.is_contiguous()
+        return ctypes.c_void_p(t.data_ptr())
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(np.asarray(p, dtype=np.float32).reshape(-1))
+        self._check(self._L.arche_net_set_params(self._h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), p.size))
+
+    def params(self):
+        p = np.empty(self.n_params, dtype=np.float32)
+        self._check(self._L.arche_net_get_params(self._h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), p.size))
+        return p
+
+    def grads(self):
+        p = np.empty(self.n_params, dtype=np.float32)
+        self._check(self._L.arche_net_get_grads(self._h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), p.size))
+        return p
+
+    def forward(self, guess, prev, n0, r_out):
+        self._check(self._L.arche_net_forward(self._h, self._dev(guess), self._dev(prev), float(n0), self._dev(r_out)))
+
+    def propose(self, guess, prev, n0, n_out):
+        self._check(self._L.arche_net_propose(self._h, self._dev(guess), self._dev(prev), float(n0), self._dev(n_out)))
+
+    def loss_grad(self, guess, prev, conv, n0):
+        loss = ctypes.c_double(0.0)
+        self._check(self._L.arche_net_loss_grad(self._h, self._dev(guess), self._dev(prev), self._dev(conv),
+                                                float(n0), ctypes.byref(loss)))
+        return loss.value
+
+    def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        self._check(self._L.arche_net_adam_step(self._h, float(lr), float(beta1), float(beta2), float(eps)))
+
+    def debug(self, which, level):
+        g = [x >> level for x in self.grid]
+        out = np.empty((g[0], g[1], g[2], 32), dtype=np.float32)
+        self._check(self._L.arche_net_debug_get(self._h, int(which), int(level),
+                                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return out
+
+    def sync(self):
+        self._check(self._L.arche_net_sync(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.arche_net_free(self._h)
             self._h = None
 
     def __del__(self):

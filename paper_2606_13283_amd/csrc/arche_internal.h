@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "../../include/arche.h"
+#include "../../include/arche_net.h"
 #include "common.h"
 #include "fft.h"
 #include "profile.h"
@@ -170,6 +171,7 @@ struct arche_ctx {
   bool iter_built = false, fused = false;
   ActiveArgs active{};
   std::vector<IterStep> steps;
+  arche_net* init_net = nullptr;  // learned initial density (not owned)
 };
 
 // device Fermi-Dirac tables (uploaded once per process and device)
@@ -187,6 +189,8 @@ hipError_t scf_vw_laplacian(arche_ctx* c, const double* n, double* lap);  // lap
 hipError_t scf_energies(arche_ctx* c, double* out16);  // see scf.hip for the order
 hipError_t scf_initial_uniform(arche_ctx* c);
 hipError_t scf_initial_one_center(arche_ctx* c, int* used_fallback);  // ionic.hip
+hipError_t scf_one_center_density(arche_ctx* c, int* used_fallback);  // n_i only (ionic.hip)
+hipError_t scf_floor_renorm(arche_ctx* c, double* n, bool* ok);       // ionic.hip
 hipError_t scf_prepare_input(arche_ctx* c);  // n^_i, V_H, lap sqrt(n_i) from n_i
 int scf_coop_blocks(int64_t ng);
 // the iteration's launch arguments (fills c->active, c->steps, c->fused)

@@ -356,6 +356,10 @@ __global__ void __launch_bounds__(ARCHE_BLOCK) k_floor(double* n, int64_t ng, do
   if (threadIdx.x == 0) part[gridDim.x + blockIdx.x] = fl;
 }
 
+__global__ void __launch_bounds__(ARCHE_BLOCK) k_fill_ni(double* n, int64_t ng, double v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ng; i += (int64_t)gridDim.x * blockDim.x) n[i] = v;
+}
+
 __global__ void __launch_bounds__(ARCHE_BLOCK) k_scale(double* n, int64_t ng, double s) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ng; i += (int64_t)gridDim.x * blockDim.x) n[i] *= s;
 }
@@ -498,7 +502,29 @@ hipError_t ionic_shells(arche_ctx* c) {
 // One-center initial density (Sec. 2.5.1) from the previous converged step:
 // g per shell, n^_i = g (SZ+ + SZ-)/2 at the new positions, C2R, floor at
 // 1e-12 n_0 and rescale to N_e; uniform if the floor added more than 1e-6 N_e.
-hipError_t scf_initial_one_center(arche_ctx* c, int* used_fallback) {
+// Floor n at 1e-12 n0 and rescale it to N_e electrons; *ok = false (n left
+// floored, not rescaled) when the floor changed the charge beyond rounding or
+// the result is not finite.
+hipError_t scf_floor_renorm(arche_ctx* c, double* n, bool* ok) {
+  const GridInfo& g = c->g;
+  const double n0 = c->Ne / g.vol;
+  const int nb = red_blocks(g.ng);
+  hipLaunchKernelGGL(k_floor, dim3(nb), dim3(ARCHE_BLOCK), 0, c->stream, n, g.ng, 1e-12 * n0, c->partials);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(finish_sums(c->partials, nb, 1, c->sums, c->stream));
+  HIP_TRY(finish_sums(c->partials + nb, nb, 1, c->sums + 1, c->stream));
+  double h[2];
+  HIP_TRY(hipMemcpyAsync(h, c->sums, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  const double raw = g.dv * h[0], fl = g.dv * h[1];
+  *ok = std::fabs(fl - raw) <= 1e-6 * c->Ne && fl > 0.0 && std::isfinite(fl);
+  if (!*ok) return hipSuccess;
+  hipLaunchKernelGGL(k_scale, dim3(grid_for(g.ng)), dim3(ARCHE_BLOCK), 0, c->stream, n, g.ng, c->Ne / fl);
+  return hipGetLastError();
+}
+
+// n_i = the one-center guess (Sec. 2.5.1), without the derived fields
+hipError_t scf_one_center_density(arche_ctx* c, int* used_fallback) {
   const GridInfo& g = c->g;
   *used_fallback = 0;
   hipLaunchKernelGGL(k_shell_profile, dim3((c->nshell + ARCHE_BLOCK - 1) / ARCHE_BLOCK), dim3(ARCHE_BLOCK), 0,
@@ -509,21 +535,17 @@ hipError_t scf_initial_one_center(arche_ctx* c, int* used_fallback) {
                      c->shell_of, c->SZp, c->SZm, g, c->ctmp);
   HIP_TRY(hipGetLastError());
   HIP_TRY(fft_c2r(&c->plan, c->ctmp, c->n_i, 1.0 / g.vol, c->stream));
-  const double n0 = c->Ne / g.vol;
-  const int nb = red_blocks(g.ng);
-  hipLaunchKernelGGL(k_floor, dim3(nb), dim3(ARCHE_BLOCK), 0, c->stream, c->n_i, g.ng, 1e-12 * n0, c->partials);
-  HIP_TRY(hipGetLastError());
-  HIP_TRY(finish_sums(c->partials, nb, 1, c->sums, c->stream));
-  HIP_TRY(finish_sums(c->partials + nb, nb, 1, c->sums + 1, c->stream));
-  double h[2];
-  HIP_TRY(hipMemcpyAsync(h, c->sums, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(hipStreamSynchronize(c->stream));
-  const double raw = g.dv * h[0], fl = g.dv * h[1];
-  if (!(std::fabs(fl - raw) <= 1e-6 * c->Ne) || !(fl > 0.0)) {
+  bool ok = false;
+  HIP_TRY(scf_floor_renorm(c, c->n_i, &ok));
+  if (!ok) {
     *used_fallback = 1;
-    return scf_initial_uniform(c);
+    hipLaunchKernelGGL(k_fill_ni, dim3(grid_for(g.ng)), dim3(ARCHE_BLOCK), 0, c->stream, c->n_i, g.ng, c->Ne / g.vol);
+    HIP_TRY(hipGetLastError());
   }
-  hipLaunchKernelGGL(k_scale, dim3(grid_for(g.ng)), dim3(ARCHE_BLOCK), 0, c->stream, c->n_i, g.ng, c->Ne / fl);
-  HIP_TRY(hipGetLastError());
+  return hipSuccess;
+}
+
+hipError_t scf_initial_one_center(arche_ctx* c, int* used_fallback) {
+  HIP_TRY(scf_one_center_density(c, used_fallback));
   return scf_prepare_input(c);
 }

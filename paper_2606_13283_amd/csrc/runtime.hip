@@ -116,7 +116,7 @@ arche_status validate(const arche_params* p, std::string& msg) {
   if (!(p->w_fixed >= 0.0 && p->w_fixed < 1.0)) return msg = "w_fixed must be in [0, 1)", ARCHE_EINVAL;
   if (p->more_warmup < 0) return msg = "more_warmup must be >= 0", ARCHE_EINVAL;
   if (!(p->more_trust > 0.0)) return msg = "more_trust must be positive", ARCHE_EINVAL;
-  if (p->init < ARCHE_INIT_UNIFORM || p->init > ARCHE_INIT_KEEP) return msg = "unknown init", ARCHE_EINVAL;
+  if (p->init < ARCHE_INIT_UNIFORM || p->init > ARCHE_INIT_LEARNED) return msg = "unknown init", ARCHE_EINVAL;
   return ARCHE_OK;
 }
 
@@ -231,8 +231,24 @@ arche_status begin_solve(arche_ctx* c, const double* pos_host, int init, int* fa
   CK(hipMemcpyAsync(c->pos, c->h_pos.data(), 3 * n * sizeof(double), hipMemcpyHostToDevice, c->stream));
   CK(ionic_structure(c));
   *fallback = 0;
-  if (init == ARCHE_INIT_ONE_CENTER && c->have_prev) {
+  if (init == ARCHE_INIT_LEARNED && c->have_prev && c->init_net) {
+    // one-center guess -> n_i; proposal from [n_i, previous converged n_a] -> rtmp
+    CK(scf_one_center_density(c, fallback));
+    bool ok = false;
+    if (!*fallback) {
+      CK(hipStreamSynchronize(c->stream));
+      arche_status s = arche_net_propose(c->init_net, c->n_i, c->n_a, c->Ne / c->g.vol, c->rtmp);
+      if (s != ARCHE_OK) return set_err(c, s, std::string("learned guess: ") + arche_net_last_error(c->init_net));
+      s = arche_net_sync(c->init_net);
+      if (s != ARCHE_OK) return set_err(c, s, std::string("learned guess: ") + arche_net_last_error(c->init_net));
+      CK(scf_floor_renorm(c, c->rtmp, &ok));
+      if (ok) CK(hipMemcpyAsync(c->n_i, c->rtmp, c->g.ng * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    }
+    if (!ok) *fallback = 1;
+    CK(scf_prepare_input(c));
+  } else if ((init == ARCHE_INIT_ONE_CENTER || init == ARCHE_INIT_LEARNED) && c->have_prev) {
     CK(scf_initial_one_center(c, fallback));
+    if (init == ARCHE_INIT_LEARNED) *fallback = 1;
   } else if (init == ARCHE_INIT_KEEP && c->solved) {
     CK(scf_prepare_input(c));
   } else {
@@ -509,6 +525,12 @@ arche_status arche_set_density(arche_ctx* c, const double* src, int32_t on_devic
   CK(hipStreamSynchronize(c->stream));
   c->solved = true;  // an input density exists for ARCHE_INIT_KEEP
   c->converged = false;
+  return ARCHE_OK;
+}
+
+arche_status arche_set_init_net(arche_ctx* c, arche_net* net) {
+  if (!c) return ARCHE_EINVAL;
+  c->init_net = net;
   return ARCHE_OK;
 }
 

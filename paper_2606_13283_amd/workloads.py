@@ -147,6 +147,19 @@ def fcc256(seed: int = 2, steps: int = 50) -> Workload:
                     seed=seed)
 
 
+def fcc256_at(T_ev: float, seed: int, steps: int = 50) -> Workload:
+    """The 256-atom fcc cell at 2.7 g/cm^3 and 64^3 at temperature T_ev (eV), with
+    Maxwell-Boltzmann velocities from `seed`: the trajectories the learned
+    initial density is trained and evaluated on."""
+    L = cell_length(256, 2.7)
+    rng = np.random.default_rng(seed)
+    pos = fcc_positions(4, L)
+    kT = ev(T_ev)
+    vel = mb_velocities(256, kT, AL_MASS, rng)
+    return Workload("fcc256_64^3_%geV" % T_ev, (L, L, L), (64, 64, 64), pos, kT, vel=vel, steps=steps, seed=seed,
+                    w_fixed=0.99 if T_ev < 3.0 else 0.95)
+
+
 def batch_snapshot(i: int) -> Workload:
     seed = 3000 + i
     rng = np.random.default_rng(seed)

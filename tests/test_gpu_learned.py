@@ -1,0 +1,76 @@
+"""The learned initial density in the SCF: trained on the GPU by the
+library's own kernels on samples the method generates (256 Al, 64^3, 2.7
+g/cm^3, 2-10 eV), then judged on a held-out trajectory by the SCF iterations
+it saves against the one-center guess at the same converged answer; and the
+fallback to the plain guess when the proposal is unusable."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2606_13283_amd import arche
+from paper_2606_13283_amd import learned as LN
+from paper_2606_13283_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    arche.load()
+
+
+def test_param_layout_count():
+    assert sum(int(np.prod(s)) for _, s in LN.param_layout()) == arche.load().arche_net_param_count()
+
+
+@pytest.fixture(scope="module")
+def trained():
+    ws = [W.fcc256_at(T, seed=100 + i) for i, T in enumerate((2.0, 4.0, 6.0, 8.0, 10.0))]
+    samples = LN.generate(ws, steps=16)
+    say("samples", len(samples))
+    net = arche.Net((64, 64, 64))
+    net.set_params(LN.init_params(0))
+    data = [s for s, _ in samples]
+    n0s = [LN.n0_of(ws[0])] * len(data)
+    hist = LN.train(net, data, n0s, epochs=12, lr=1e-3)
+    say("loss per epoch", ["%.3e" % h for h in hist])
+    return net, hist
+
+
+def test_training_converges(trained):
+    net, hist = trained
+    assert hist[-1] < 0.5 * hist[0]
+
+
+def test_learned_guess_saves_iterations(trained):
+    net, _ = trained
+    rows = LN.compare(W.fcc256_at(5.0, seed=300), net, steps=8)
+    for r in rows:
+        say(r)
+        assert r["fallback"] == 0
+        assert abs(r["F_learned"] - r["F_plain"]) <= 1e-9 * abs(r["F_plain"])
+    plain = np.mean([r["plain_iters"] for r in rows])
+    lrn = np.mean([r["learned_iters"] for r in rows])
+    say("mean SCF iterations: one-center %.1f, learned %.1f" % (plain, lrn))
+    assert lrn < plain
+
+
+def test_unusable_proposal_falls_back():
+    net = arche.Net((64, 64, 64))
+    p = LN.init_params(1)
+    p[-1] = -10.0  # out.b: proposal n = g - 10 n0, negative everywhere
+    net.set_params(p)
+    w = W.fcc256_at(5.0, seed=301)
+    tr = LN.Trajectory(w, init=arche.INIT_LEARNED, net=net)
+    res, _ = tr.step()
+    assert res["converged"] and res["used_fallback"] == 1
+    tr.close()
+    net.close()
