@@ -55,7 +55,10 @@ arche_status arche_debug_one_center(arche_ctx *ctx, const double *pos_host, doub
 
 /* Per-kernel timing.  When enabled, every launch of the kernels below made by
  * calls on ctx is bracketed by a pair of hipEvents on the context's stream and
- * the elapsed times are summed (the events add a few microseconds per launch).
+ * the elapsed times are summed.  Each event pair costs about 10 us of idle GPU
+ * time between launches, so time only the kinds needed: on = 0 disables,
+ * on = 1 times every kind, any other value times the kinds whose bit is set in
+ * on >> 1 (e.g. 2 << ARCHE_PROF_SCF_ACTIVE for the SCF kernel alone).
  *   ARCHE_PROF_SCF_ACTIVE   the cooperative kernel of one SCF iteration
  *                           (potential, Newton search of mu, active density)
  *   ARCHE_PROF_FFT_Z        the z passes of the 3D FFTs (R2C and C2R)
@@ -65,6 +68,15 @@ arche_status arche_profile_enable(arche_ctx *ctx, int32_t on);
 arche_status arche_profile_reset(arche_ctx *ctx);
 /* ESTATE unless profiling is enabled; EINVAL for an unknown kind */
 arche_status arche_profile_read(arche_ctx *ctx, int32_t kind, double *total_ms, int64_t *launches);
+
+/* FFT tile variant in use for line length L in pass 0 (y), 1 (x) or 2 (z):
+ * 0 = 16 columns (strided) / 32 or 16 row pairs (z) per 256-thread block,
+ * 1 = 8 per 128 threads, 2 = 4 per 64 threads (lengths above 96 only).  The
+ * first context of a length times the variants and keeps the fastest
+ * (ARCHE_FFT_TUNE=0 disables).  force in {0,1,2} sets the variant for contexts
+ * created afterwards (force < 0: query only).  Returns the variant, -1 for a
+ * bad argument. */
+int32_t arche_fft_tile(int32_t pass, int32_t L, int32_t force);
 
 #ifdef __cplusplus
 }

@@ -48,6 +48,33 @@ def I_p32(x):
     return fd_integrals(x, ("p32",))["p32"]
 
 
+def I_p12_inverse_array(y, x0=None):
+    """Element-wise X(y) with I_{1/2}(X) = y for an array y > 0: Newton
+    safeguarded by bisection inside the bracket lo = ln(y / Gamma(3/2))
+    (I_{1/2}(x) < Gamma(3/2) e^x) and hi = max((3y/2)^{2/3}, lo + 1) + 1
+    (I_{1/2}(x) > x^{3/2} / (3/2) for x > 0), started from x0 when given."""
+    y = np.asarray(y, dtype=np.float64)
+    if not np.all(y > 0.0):
+        raise ValueError("I_{1/2}^{-1} needs y > 0")
+    lo = np.log(y / math.gamma(1.5)) - 1e-9
+    hi = np.maximum((1.5 * y) ** (2.0 / 3.0), lo + 1.0) + 1.0
+    x = 0.5 * (lo + hi) if x0 is None else np.clip(np.asarray(x0, dtype=np.float64), lo, hi)
+    done = np.zeros(y.shape, dtype=bool)
+    for _ in range(200):
+        v = fd_integrals(x, ("m12", "p12"))
+        f = v["p12"] - y
+        hi = np.where(~done & (f > 0), x, hi)
+        lo = np.where(~done & (f <= 0), x, lo)
+        xn = x - f / (0.5 * v["m12"])
+        xn = np.where((lo < xn) & (xn < hi), xn, 0.5 * (lo + hi))
+        fin = np.abs(xn - x) <= 2e-16 * np.maximum(1.0, np.abs(x))
+        x = np.where(done, x, xn)
+        done |= fin
+        if done.all():
+            return x
+    raise RuntimeError("I_{1/2}^{-1} did not converge")
+
+
 def I_p12_inverse(y: float) -> float:
     """X(y) with I_{1/2}(X) = y, y > 0 (Sec. 2.4).  Safeguarded Newton on the
     monotone I_{1/2}, derivative dI_{1/2}/dx = (1/2) I_{-1/2}."""

@@ -13,15 +13,21 @@ One iteration, with input density n_i (Sec. 2.5 and its subsections):
      w = w_fixed throughout.  More mixing uses w_fixed until it is switched
      on, then w = U / (U + K) clamped to [0, 0.995], with
         U = -int (dF/dn at n_a) Delta n = int (V_i - V_eff[n_a]) Delta n
-        K = int Delta n^2 / (dn_a/dmu)
+        K = int kT (eta(n_i) - eta_a) Delta n,  eta(n) = I_{1/2}^{-1}(n / c_n)
      Readings (the paper states U only for the Hartree term and says adding
-     the other potential terms is straightforward; it switches More's weight
-     on "after a few iterations, once the chemical potential fluctuations are
-     small"): U keeps every potential term -- Hartree, xc and vW -- as the
-     secant difference above (with vW present the Hartree-only U drives the
-     stiff short-wavelength vW modes unstable); the switch happens at the first
-     iteration t >= warmup at which the second-order expansion behind the
-     weight holds pointwise, max_r |Delta n| / n_a <= more_trust (0.5), and is
+     the other potential terms is straightforward; its K is the second-order
+     form int Delta n^2 / (dn_a/dmu); it switches More's weight on "after a
+     few iterations, once the chemical potential fluctuations are small"):
+     U keeps every potential term -- Hartree, xc and vW -- as the secant
+     difference above (with vW present the Hartree-only U drives the stiff
+     short-wavelength vW modes unstable); K is taken as the same kind of secant
+     of the Thomas-Fermi potential kT eta(n), which equals the paper's K to
+     second order in Delta n but stays bounded where n_i / n_a is large (low
+     density regions at low T, where the second-order K grows like n_i / n_a,
+     drives w to 0 and the iteration diverges); the switch happens at the first
+     iteration t >= warmup at which either the second-order expansion behind
+     the weight holds pointwise, max_r |Delta n| / n_a <= more_trust (0.5), or
+     mu moved by at most MU_SETTLED kT since the previous iteration, and is
      never undone.
   6. n_o = n_a + w Delta n becomes the next n_i.
 
@@ -212,6 +218,11 @@ class SCFResult:
     used_fallback: bool = False
 
 
+# More's weight may switch on once mu moves by at most this fraction of kT
+# between iterations (the paper's "mu fluctuations are small")
+MU_SETTLED = 0.02
+
+
 def scf(sys: System, ion: Ionic, n_init: np.ndarray, mixing="more", tol=1e-10, max_iter=5000,
         warmup=3, w_fixed=0.95, more_trust=0.5, mu0=None) -> SCFResult:
     g = sys.grid
@@ -224,23 +235,27 @@ def scf(sys: System, ion: Ionic, n_init: np.ndarray, mixing="more", tol=1e-10, m
     n_a = eta = V = None
     for t in range(max_iter):
         V, _ = effective_potential(sys, ion, n_i)
+        mu_prev = mu
         mu, nit = solve_mu(sys, V, mu)
         newt.append(nit)
         eta = (mu - V) / sys.kT
         v = fd.fd_integrals(eta, ("m12", "p12"))
         n_a = cn * v["p12"]
-        chi = cn / (2.0 * sys.kT) * v["m12"]
         dn = n_i - n_a
         r = math.sqrt(float(np.sum(dn * dn)) / float(np.sum(n_a * n_a)))
         hist.append(r)
         if r < tol:
             return SCFResult(n_a, eta, mu, V, t + 1, r, True, hist, newt, ws)
         if mixing == "more" and not more_on and t >= warmup:
-            more_on = float(np.max(np.abs(dn) / n_a)) <= more_trust
+            more_on = (float(np.max(np.abs(dn) / n_a)) <= more_trust
+                       or (mu_prev is not None and abs(mu - mu_prev) <= MU_SETTLED * sys.kT))
         if more_on:
+            # U and K are the secants of the interaction and of the Thomas-Fermi
+            # potential between n_a and n_i along dn (K -> int dn^2/chi as dn -> 0)
             Va, _ = effective_potential(sys, ion, n_a)
             U = g.integrate((V - Va) * dn)
-            K = g.integrate(dn * dn / chi)
+            eta_i = fd.I_p12_inverse_array(n_i / cn, eta)
+            K = g.integrate(sys.kT * (eta_i - eta) * dn)
             w = min(max(U / (U + K), 0.0), 0.995)
         else:
             w = w_fixed

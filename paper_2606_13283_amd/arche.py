@@ -148,6 +148,8 @@ def load(path: str = LIB_PATH):
     L.arche_net_free.restype = None
     L.arche_set_init_net.argtypes = [vp, vp]
     L.arche_set_init_net.restype = st
+    L.arche_fft_tile.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    L.arche_fft_tile.restype = ctypes.c_int32
     L.arche_k_fft_r2c.argtypes = [_ip, vp, vp, vp]
     L.arche_k_fft_r2c.restype = st
     L.arche_k_fft_c2r.argtypes = [_ip, vp, vp, vp]
@@ -296,8 +298,15 @@ class Context:
         self._check(self._L.arche_debug_one_center(self._h, _ptr(pos), _ptr(out), ctypes.byref(fb)))
         return out, bool(fb.value)
 
-    def profile(self, on=True):
-        self._check(self._L.arche_profile_enable(self._h, 1 if on else 0))
+    def profile(self, on=True, kinds=None):
+        """Per-kernel event timing; kinds: names from PROF_NAMES (default all)."""
+        if not on:
+            code = 0
+        elif kinds is None:
+            code = 1
+        else:
+            code = sum(2 << PROF_NAMES.index(k) for k in kinds)
+        self._check(self._L.arche_profile_enable(self._h, code))
 
     def profile_reset(self):
         self._check(self._L.arche_profile_reset(self._h))

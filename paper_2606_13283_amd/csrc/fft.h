@@ -101,6 +101,7 @@ struct FftPass {
   int kind;        // FFT_PASS_*
   int L;           // line length
   int sign, mode;  // strided: transform sign and MODE; z passes: FIN or FOUT code
+  int var;         // tile variant (fft_tune)
   unsigned nblocks;
   StridedArgs s;   // FFT_PASS_STRIDED
   ZArgs z;         // the z passes
@@ -112,6 +113,17 @@ bool fft_r2c_passes(const FftPlan* p, const double* in, cplx* out, double in_sca
 bool fft_c2r_passes(const FftPlan* p, const cplx* in, cplx* work, double* out, double out_scale, int fin, int fout,
                     const FftFuse& f, FftPass out3[3]);
 hipError_t fft_pass_launch(const FftPass& ps, hipStream_t s);
+
+// Tile autotuner: for each line length of the plan outside the batched set,
+// time the tile variants of the y, x and z passes on the scratch arrays (any
+// contents) and keep the fastest for the rest of the process (the first plan of
+// a length decides; later plans reuse it).  A variant changes which block sums
+// which terms of the fused partial sums, so results agree to rounding across
+// variants and are reproducible for a fixed choice.  ARCHE_FFT_TUNE=0 in the
+// environment keeps the default tiles.
+hipError_t fft_tune(const FftPlan* p, cplx* scratch_c, double* scratch_r, hipStream_t s);
+// the variant in use for (pass 0 y / 1 x / 2 z, line length); force >= 0 sets it
+int fft_tile_variant(int pass, int L, int force);
 
 // Batched passes (fft_batch.hip): one launch runs the jobs[j] (device array of
 // FftPass, all of the same kind, sign and mode, line lengths within

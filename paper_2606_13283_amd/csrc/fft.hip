@@ -5,6 +5,8 @@
 
 #include <cmath>
 #include <cstring>
+#include <cstdlib>
+#include <mutex>
 #include <vector>
 
 namespace {
@@ -257,51 +259,85 @@ k_fft_strided(cplx* __restrict__ data, const cplx* __restrict__ tw_g, int L, int
 // once it is set (a converged SCF).
 __device__ inline bool fft_stopped(const FftFuse& f) { return f.stop && *f.stop; }
 
-template <int L, int TK, int S, int MODE>
-__global__ void __launch_bounds__(ARCHE_BLOCK) k_strided_ct(StridedArgs A) {
+template <int L, int TK, int S, int MODE, int NT>
+__global__ void __launch_bounds__(NT) k_strided_ct(StridedArgs A) {
   if (fft_stopped(A.f)) return;
   __shared__ cplx lds[strided_lds<L, TK>()];
   __shared__ cplx tw[L];
-  __shared__ double sh[ARCHE_BLOCK / 64];
-  strided_body<L, TK, S, MODE>(A, blockIdx.x, lds, tw, sh);
+  __shared__ double sh[NT / 64];
+  strided_body<L, TK, S, MODE, NT>(A, blockIdx.x, lds, tw, sh);
 }
 
-template <int L, int B, int FIN>
-__global__ void __launch_bounds__(ARCHE_BLOCK) k_z_r2c_ct(ZArgs A) {
+template <int L, int B, int FIN, int NT>
+__global__ void __launch_bounds__(NT) k_z_r2c_ct(ZArgs A) {
   if (fft_stopped(A.f)) return;
   __shared__ cplx lds[z_r2c_lds<L, B>()];
   __shared__ cplx tw[L];
-  z_r2c_body<L, B, FIN>(A, blockIdx.x, lds, tw);
+  z_r2c_body<L, B, FIN, NT>(A, blockIdx.x, lds, tw);
 }
 
-template <int L, int B, int FOUT>
-__global__ void __launch_bounds__(ARCHE_BLOCK) k_z_c2r_ct(ZArgs A) {
+template <int L, int B, int FOUT, int NT>
+__global__ void __launch_bounds__(NT) k_z_c2r_ct(ZArgs A) {
   if (fft_stopped(A.f)) return;
   __shared__ cplx lds[z_c2r_lds<L, B>()];
   __shared__ cplx tw[L];
-  __shared__ double sh[ARCHE_BLOCK / 64];
-  z_c2r_body<L, B, FOUT>(A, blockIdx.x, lds, tw, sh);
+  __shared__ double sh[NT / 64];
+  z_c2r_body<L, B, FOUT, NT>(A, blockIdx.x, lds, tw, sh);
+}
+
+// Tile variants (autotuned per line length, fft.h): strided passes take TK
+// columns per block with NT threads, z passes B row pairs with NT threads.
+// Variant 0 is the default; line lengths of the batched set use only it.
+constexpr int kStridedTK[3] = {CT_TK, 8, 4};
+constexpr int kStridedNT[3] = {ARCHE_BLOCK, 128, 64};
+template <int L>
+constexpr bool tunable() {
+  return L > 96;
+}
+template <int L>
+constexpr int z_rows_var(int v) {
+  return v == 0 ? ct_rows<L>() : (v == 1 ? 8 : 4);
+}
+constexpr int kZNT[3] = {ARCHE_BLOCK, 128, 64};
+
+template <int L, int TK, int NT>
+hipError_t launch_strided_tile(const FftPass& ps, hipStream_t s) {
+  const dim3 grid(ps.nblocks), blk(NT);
+  if (ps.mode == 0 && ps.sign < 0) hipLaunchKernelGGL((k_strided_ct<L, TK, -1, 0, NT>), grid, blk, 0, s, ps.s);
+  else if (ps.mode == 0) hipLaunchKernelGGL((k_strided_ct<L, TK, +1, 0, NT>), grid, blk, 0, s, ps.s);
+  else if (ps.mode == 1) hipLaunchKernelGGL((k_strided_ct<L, TK, -1, 1, NT>), grid, blk, 0, s, ps.s);
+  else if (ps.mode == 2) hipLaunchKernelGGL((k_strided_ct<L, TK, -1, 2, NT>), grid, blk, 0, s, ps.s);
+  else hipLaunchKernelGGL((k_strided_ct<L, TK, +1, 3, NT>), grid, blk, 0, s, ps.s);
+  return hipGetLastError();
+}
+template <int L, int B, int NT>
+hipError_t launch_z_tile(const FftPass& ps, hipStream_t s) {
+  const dim3 grid(ps.nblocks), blk(NT);
+  if (ps.kind == FFT_PASS_Z_R2C) {
+    if (ps.mode == 0) hipLaunchKernelGGL((k_z_r2c_ct<L, B, 0, NT>), grid, blk, 0, s, ps.z);
+    else if (ps.mode == 1) hipLaunchKernelGGL((k_z_r2c_ct<L, B, 1, NT>), grid, blk, 0, s, ps.z);
+    else hipLaunchKernelGGL((k_z_r2c_ct<L, B, 2, NT>), grid, blk, 0, s, ps.z);
+  } else {
+    if (ps.mode == 0) hipLaunchKernelGGL((k_z_c2r_ct<L, B, 0, NT>), grid, blk, 0, s, ps.z);
+    else hipLaunchKernelGGL((k_z_c2r_ct<L, B, 1, NT>), grid, blk, 0, s, ps.z);
+  }
+  return hipGetLastError();
 }
 
 template <int L>
 hipError_t launch_pass(const FftPass& ps, hipStream_t s) {
-  constexpr int B = ct_rows<L>();
-  const dim3 grid(ps.nblocks), blk(ARCHE_BLOCK);
   if (ps.kind == FFT_PASS_STRIDED) {
-    if (ps.mode == 0 && ps.sign < 0) hipLaunchKernelGGL((k_strided_ct<L, CT_TK, -1, 0>), grid, blk, 0, s, ps.s);
-    else if (ps.mode == 0) hipLaunchKernelGGL((k_strided_ct<L, CT_TK, +1, 0>), grid, blk, 0, s, ps.s);
-    else if (ps.mode == 1) hipLaunchKernelGGL((k_strided_ct<L, CT_TK, -1, 1>), grid, blk, 0, s, ps.s);
-    else if (ps.mode == 2) hipLaunchKernelGGL((k_strided_ct<L, CT_TK, -1, 2>), grid, blk, 0, s, ps.s);
-    else hipLaunchKernelGGL((k_strided_ct<L, CT_TK, +1, 3>), grid, blk, 0, s, ps.s);
-  } else if (ps.kind == FFT_PASS_Z_R2C) {
-    if (ps.mode == 0) hipLaunchKernelGGL((k_z_r2c_ct<L, B, 0>), grid, blk, 0, s, ps.z);
-    else if (ps.mode == 1) hipLaunchKernelGGL((k_z_r2c_ct<L, B, 1>), grid, blk, 0, s, ps.z);
-    else hipLaunchKernelGGL((k_z_r2c_ct<L, B, 2>), grid, blk, 0, s, ps.z);
-  } else {
-    if (ps.mode == 0) hipLaunchKernelGGL((k_z_c2r_ct<L, B, 0>), grid, blk, 0, s, ps.z);
-    else hipLaunchKernelGGL((k_z_c2r_ct<L, B, 1>), grid, blk, 0, s, ps.z);
+    if constexpr (tunable<L>()) {
+      if (ps.var == 1) return launch_strided_tile<L, kStridedTK[1], kStridedNT[1]>(ps, s);
+      if (ps.var == 2) return launch_strided_tile<L, kStridedTK[2], kStridedNT[2]>(ps, s);
+    }
+    return launch_strided_tile<L, kStridedTK[0], kStridedNT[0]>(ps, s);
   }
-  return hipGetLastError();
+  if constexpr (tunable<L>()) {
+    if (ps.var == 1) return launch_z_tile<L, z_rows_var<L>(1), kZNT[1]>(ps, s);
+    if (ps.var == 2) return launch_z_tile<L, z_rows_var<L>(2), kZNT[2]>(ps, s);
+  }
+  return launch_z_tile<L, z_rows_var<L>(0), kZNT[0]>(ps, s);
 }
 template <int L>
 constexpr int z_rows() {
@@ -335,11 +371,11 @@ hipError_t launch_pass_any(const FftPass& ps, hipStream_t s) {
       return hipErrorNotSupported;
   }
 }
-int ct_z_rows(int L) {
+int ct_z_rows(int L, int var) {
   switch (L) {
 #define X(n) \
   case n:    \
-    return z_rows<n>();
+    return tunable<n>() ? z_rows_var<n>(var) : z_rows<n>();
     ARCHE_CT_SIZES(X)
 #undef X
     default:
@@ -347,14 +383,19 @@ int ct_z_rows(int L) {
   }
 }
 
+// chosen tile variant per (line length, pass): [0] y pass, [1] x pass, [2] z pass
+int g_tile_var[3][1025];
+
 FftPass strided_desc(int L, int mode, int sign, cplx* data, const cplx* src, const cplx* tw, int64_t es, int64_t os,
-                     int nouter, int ncols, double scale, const FftFuse& f, const XGeom& g) {
+                     int nouter, int ncols, double scale, const FftFuse& f, const XGeom& g, int axis) {
   FftPass ps{};
   ps.kind = FFT_PASS_STRIDED;
   ps.L = L;
   ps.sign = sign;
   ps.mode = mode;
-  const int nchunk = (ncols + CT_TK - 1) / CT_TK;
+  ps.var = L <= 1024 ? g_tile_var[axis == 0 ? 1 : 0][L] : 0;
+  const int tk = kStridedTK[ps.var];
+  const int nchunk = (ncols + tk - 1) / tk;
   ps.nblocks = (unsigned)(nouter * nchunk);
   ps.s = StridedArgs{data, src, tw, es, os, ncols, nchunk, scale, f, g};
   return ps;
@@ -366,16 +407,17 @@ FftPass z_desc(int kind, int L, int code, const void* in, void* out, const cplx*
   ps.L = L;
   ps.sign = kind == FFT_PASS_Z_R2C ? -1 : +1;
   ps.mode = code;
-  const int B = ct_z_rows(L);
+  ps.var = L <= 1024 ? g_tile_var[2][L] : 0;
+  const int B = ct_z_rows(L, ps.var);
   ps.nblocks = (unsigned)((npairs + B - 1) / B);
   ps.z = ZArgs{in, out, tw, npairs, is, os, f};
   return ps;
 }
 
 hipError_t ct_strided(int L, int mode, int sign, cplx* data, const cplx* src, const cplx* tw, int64_t es, int64_t os,
-                      int nouter, int ncols, double scale, const FftFuse& f, const XGeom& g, hipStream_t s) {
+                      int nouter, int ncols, double scale, const FftFuse& f, const XGeom& g, int axis, hipStream_t s) {
   if (!ct_supported(L)) return hipErrorNotSupported;
-  return launch_pass_any(strided_desc(L, mode, sign, data, src, tw, es, os, nouter, ncols, scale, f, g), s);
+  return launch_pass_any(strided_desc(L, mode, sign, data, src, tw, es, os, nouter, ncols, scale, f, g, axis), s);
 }
 hipError_t ct_z_r2c(int L, int fin, const double* in, cplx* out, const cplx* tw, int64_t npairs, double is, double os,
                     const FftFuse& f, hipStream_t s) {
@@ -417,7 +459,8 @@ hipError_t strided_pass(const FftPlan* p, cplx* data, int axis, int sign, double
     nouter = Ny;
   }
   ProfScope prof(PROF_FFT_STRIDED, s);
-  if (ct_supported(ax.L)) return ct_strided(ax.L, 0, sign, data, data, ax.tw, es, os, nouter, Nh, scale, FftFuse{}, XGeom{}, s);
+  if (ct_supported(ax.L))
+    return ct_strided(ax.L, 0, sign, data, data, ax.tw, es, os, nouter, Nh, scale, FftFuse{}, XGeom{}, axis, s);
   const int TK = strided_tile(ax.L);
   const int nchunk = (Nh + TK - 1) / TK;
   const size_t lds = (size_t)(2 * ax.L * TK + ax.L) * sizeof(cplx);
@@ -536,10 +579,13 @@ hipError_t fft_c2r(const FftPlan* p, cplx* in, double* out, double out_scale, hi
 bool fft_fusable(const FftPlan* p) {
   return ct_supported(p->N[0]) && ct_supported(p->N[1]) && ct_supported(p->N[2]);
 }
-int fft_x_blocks(const FftPlan* p) { return p->N[1] * ((p->Nh + CT_TK - 1) / CT_TK); }
+int fft_x_blocks(const FftPlan* p) {
+  const int tk = kStridedTK[p->N[0] <= 1024 ? g_tile_var[1][p->N[0]] : 0];
+  return p->N[1] * ((p->Nh + tk - 1) / tk);
+}
 int fft_z_blocks(const FftPlan* p) {
   const int64_t npairs = (int64_t)p->N[0] * p->N[1] / 2;
-  const int B = ct_z_rows(p->N[2]);
+  const int B = ct_z_rows(p->N[2], g_tile_var[2][p->N[2]]);
   return B ? (int)((npairs + B - 1) / B) : 0;
 }
 
@@ -553,10 +599,11 @@ bool fft_r2c_passes(const FftPlan* p, const double* in, cplx* out, double in_sca
   const int64_t npairs = (int64_t)p->N[0] * p->N[1] / 2;
   const int Nh = p->Nh;
   o[0] = z_desc(FFT_PASS_Z_R2C, p->N[2], fin, in, out, p->ax[2].tw, npairs, in_scale, 1.0, f);
-  o[1] = strided_desc(p->N[1], 0, -1, out, out, p->ax[1].tw, Nh, (int64_t)p->N[1] * Nh, p->N[0], Nh, 1.0, f, XGeom{});
+  o[1] = strided_desc(p->N[1], 0, -1, out, out, p->ax[1].tw, Nh, (int64_t)p->N[1] * Nh, p->N[0], Nh, 1.0, f, XGeom{},
+                      1);
   const int mode = fout == R2C_OUT_LAP ? 1 : (fout == R2C_OUT_UH ? 2 : 0);
   o[2] = strided_desc(p->N[0], mode, -1, out, out, p->ax[0].tw, (int64_t)p->N[1] * Nh, Nh, p->N[1], Nh, out_scale, f,
-                      xgeom(p, f));
+                      xgeom(p, f), 0);
   return true;
 }
 
@@ -566,8 +613,9 @@ bool fft_c2r_passes(const FftPlan* p, const cplx* in, cplx* work, double* out, d
   const int64_t npairs = (int64_t)p->N[0] * p->N[1] / 2;
   const int Nh = p->Nh;
   o[0] = strided_desc(p->N[0], fin == C2R_IN_MIX ? 3 : 0, +1, work, fin == C2R_IN_MIX ? in : work, p->ax[0].tw,
-                      (int64_t)p->N[1] * Nh, Nh, p->N[1], Nh, 1.0, f, xgeom(p, f));
-  o[1] = strided_desc(p->N[1], 0, +1, work, work, p->ax[1].tw, Nh, (int64_t)p->N[1] * Nh, p->N[0], Nh, 1.0, f, XGeom{});
+                      (int64_t)p->N[1] * Nh, Nh, p->N[1], Nh, 1.0, f, xgeom(p, f), 0);
+  o[1] = strided_desc(p->N[1], 0, +1, work, work, p->ax[1].tw, Nh, (int64_t)p->N[1] * Nh, p->N[0], Nh, 1.0, f, XGeom{},
+                      1);
   o[2] = z_desc(FFT_PASS_Z_C2R, p->N[2], fout, work, out, p->ax[2].tw, npairs, 1.0, out_scale, f);
   return true;
 }
@@ -597,4 +645,80 @@ hipError_t fft_c2r_fused(const FftPlan* p, const cplx* in, cplx* work, double* o
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// Tile autotuner (fft.h).
+static std::mutex g_tune_mtx;
+static bool g_tuned[3][1025];
+
+int fft_tile_variant(int pass, int L, int force) {
+  if (pass < 0 || pass > 2 || L < 0 || L > 1024) return -1;
+  std::lock_guard<std::mutex> lk(g_tune_mtx);
+  if (force >= 0 && force <= 2 && (force == 0 || (ct_supported(L) && L > 96))) {
+    g_tile_var[pass][L] = force;
+    g_tuned[pass][L] = true;
+  }
+  return g_tile_var[pass][L];
+}
+
+hipError_t fft_tune(const FftPlan* p, cplx* scratch_c, double* scratch_r, hipStream_t s) {
+  const char* env = getenv("ARCHE_FFT_TUNE");
+  if (env && env[0] == '0') return hipSuccess;
+  std::lock_guard<std::mutex> lk(g_tune_mtx);
+  const int Nh = p->Nh;
+  const int64_t npairs = (int64_t)p->N[0] * p->N[1] / 2;
+  const int Ls[3] = {p->N[1], p->N[0], p->N[2]};
+  bool any = false;
+  for (int pass = 0; pass < 3; ++pass)
+    any = any || (Ls[pass] > 96 && ct_supported(Ls[pass]) && !g_tuned[pass][Ls[pass]]);
+  if (!any) return hipSuccess;
+  hipError_t e = hipMemsetAsync(scratch_c, 0, p->nh * sizeof(cplx), s);
+  if (e == hipSuccess) e = hipMemsetAsync(scratch_r, 0, p->ng * sizeof(double), s);
+  hipEvent_t t0, t1;
+  if (e == hipSuccess) e = hipEventCreate(&t0);
+  if (e != hipSuccess) return e;
+  e = hipEventCreate(&t1);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(t0);
+    return e;
+  }
+  for (int pass = 0; pass < 3 && e == hipSuccess; ++pass) {
+    const int L = Ls[pass];
+    if (L <= 96 || !ct_supported(L) || g_tuned[pass][L]) continue;
+    float best_ms = 0.f;
+    int best = 0;
+    for (int v = 0; v < 3 && e == hipSuccess; ++v) {
+      g_tile_var[pass][L] = v;
+      FftPass ps;
+      if (pass == 0)
+        ps = strided_desc(L, 0, -1, scratch_c, scratch_c, p->ax[1].tw, Nh, (int64_t)p->N[1] * Nh, p->N[0], Nh, 1.0,
+                          FftFuse{}, XGeom{}, 1);
+      else if (pass == 1)
+        ps = strided_desc(L, 0, -1, scratch_c, scratch_c, p->ax[0].tw, (int64_t)p->N[1] * Nh, Nh, p->N[1], Nh, 1.0,
+                          FftFuse{}, XGeom{}, 0);
+      else
+        ps = z_desc(FFT_PASS_Z_R2C, L, 0, scratch_r, scratch_c, p->ax[2].tw, npairs, 1.0, 1.0, FftFuse{});
+      for (int w = 0; w < 2 && e == hipSuccess; ++w) e = launch_pass_any(ps, s);
+      if (e == hipSuccess) e = hipEventRecord(t0, s);
+      for (int w = 0; w < 6 && e == hipSuccess; ++w) e = launch_pass_any(ps, s);
+      if (e == hipSuccess) e = hipEventRecord(t1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(t1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+      if (e != hipSuccess) break;
+      // a variant must beat the default by 3% to be taken
+      if (v == 0 || ms < 0.97f * best_ms) {
+        if (v == 0 || ms < best_ms) {
+          best_ms = ms;
+          best = v;
+        }
+      }
+    }
+    g_tile_var[pass][L] = e == hipSuccess ? best : 0;
+    g_tuned[pass][L] = true;
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  return e;
 }

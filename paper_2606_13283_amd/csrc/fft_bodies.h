@@ -87,9 +87,9 @@ struct ColInMix {  // C2R_IN_MIX: n_o^ = a + w (nhat_i - a); nhat_i <- n_o^; val
 
 // One tile (block `bid` of the pass).  MODE 0: plain pass.  MODE 1/2/3: x pass
 // with R2C_OUT_LAP / R2C_OUT_UH / C2R_IN_MIX.
-template <int L, int TK, int S, int MODE>
+template <int L, int TK, int S, int MODE, int NT = ARCHE_BLOCK>
 __device__ inline void strided_body(const StridedArgs& A, unsigned bid, cplx* lds, cplx* tw, double* sh) {
-  for (int i = threadIdx.x; i < L; i += ARCHE_BLOCK) tw[i] = A.tw[i];
+  for (int i = threadIdx.x; i < L; i += NT) tw[i] = A.tw[i];
   __syncthreads();
   const int o = (int)bid / A.nchunk;
   const int c0 = ((int)bid - o * A.nchunk) * TK;
@@ -97,21 +97,21 @@ __device__ inline void strided_body(const StridedArgs& A, unsigned bid, cplx* ld
   cplx* base = A.data + (int64_t)o * A.os + c0;
   const int64_t es = A.es;
   if constexpr (MODE == 0) {
-    run<L, TK, ARCHE_BLOCK, true, S, 1>(ColIn{base, es, nc}, ColOut{base, es, nc, A.scale}, lds, tw, nc,
+    run<L, TK, NT, true, S, 1>(ColIn{base, es, nc}, ColOut{base, es, nc, A.scale}, lds, tw, nc,
                                          typename Plan<L>::R{});
   } else if constexpr (MODE == 1) {
-    run<L, TK, ARCHE_BLOCK, true, S, 1>(ColIn{base, es, nc}, ColOutLap{base, es, nc, A.scale, A.g, o, c0}, lds, tw,
+    run<L, TK, NT, true, S, 1>(ColIn{base, es, nc}, ColOutLap{base, es, nc, A.scale, A.g, o, c0}, lds, tw,
                                          nc, typename Plan<L>::R{});
   } else if constexpr (MODE == 2) {
     double acc = 0.0;
-    run<L, TK, ARCHE_BLOCK, true, S, 1>(
+    run<L, TK, NT, true, S, 1>(
         ColIn{base, es, nc}, ColOutUH{base, A.f.nhat_i + (int64_t)o * A.os + c0, es, nc, A.scale, A.g, o, c0, &acc},
         lds, tw, nc, typename Plan<L>::R{});
     acc = block_sum(acc, sh);
     if (threadIdx.x == 0) A.f.partials[bid] = acc;
   } else {
     const int64_t off = (int64_t)o * A.os + c0;
-    run<L, TK, ARCHE_BLOCK, true, S, 1>(ColInMix{A.src + off, A.f.nhat_i + off, es, nc, *A.f.w, A.g, o, c0},
+    run<L, TK, NT, true, S, 1>(ColInMix{A.src + off, A.f.nhat_i + off, es, nc, *A.f.w, A.g, o, c0},
                                          ColOut{base, es, nc, A.scale}, lds, tw, nc, typename Plan<L>::R{});
   }
 }
@@ -161,26 +161,26 @@ struct PairInMix {  // R2C_IN_MIX_SQRT: n_o = n_a + w (n_i - n_a); n_i <- n_o; s
   }
 };
 
-template <int L, int B, int FIN>
+template <int L, int B, int FIN, int NT = ARCHE_BLOCK>
 __device__ inline void z_r2c_body(const ZArgs& A, unsigned bid, cplx* lds, cplx* tw) {
   constexpr int Nh = L / 2 + 1;
-  for (int i = threadIdx.x; i < L; i += ARCHE_BLOCK) tw[i] = A.tw[i];
+  for (int i = threadIdx.x; i < L; i += NT) tw[i] = A.tw[i];
   __syncthreads();
   const double* in = (const double*)A.in;
   const int64_t p0 = (int64_t)bid * B;
   const int nb = (int)((A.npairs - p0) < B ? (A.npairs - p0) : B);
   LdsIO<L, B, false> res{lds};
   if constexpr (FIN == 0)
-    run<L, B, ARCHE_BLOCK, false, -1, 1>(PairIn{in + p0 * 2 * L, L, nb, A.in_scale}, res, lds, tw, nb,
+    run<L, B, NT, false, -1, 1>(PairIn{in + p0 * 2 * L, L, nb, A.in_scale}, res, lds, tw, nb,
                                           typename Plan<L>::R{});
   else if constexpr (FIN == 1)
-    run<L, B, ARCHE_BLOCK, false, -1, 1>(PairInSqrt{in + p0 * 2 * L, L, nb, A.in_scale}, res, lds, tw, nb,
+    run<L, B, NT, false, -1, 1>(PairInSqrt{in + p0 * 2 * L, L, nb, A.in_scale}, res, lds, tw, nb,
                                           typename Plan<L>::R{});
   else
-    run<L, B, ARCHE_BLOCK, false, -1, 1>(PairInMix{in + p0 * 2 * L, A.f.n_i + p0 * 2 * L, L, nb, A.in_scale, *A.f.w},
+    run<L, B, NT, false, -1, 1>(PairInMix{in + p0 * 2 * L, A.f.n_i + p0 * 2 * L, L, nb, A.in_scale, *A.f.w},
                                           res, lds, tw, nb, typename Plan<L>::R{});
   cplx* dst = (cplx*)A.out + p0 * 2 * Nh;
-  for (int q = threadIdx.x; q < nb * 2 * Nh; q += ARCHE_BLOCK) {
+  for (int q = threadIdx.x; q < nb * 2 * Nh; q += NT) {
     const int l = q / (2 * Nh);
     const int w = q - l * 2 * Nh;
     const int r = w / Nh;
@@ -258,22 +258,22 @@ struct PairOutUvw {  // C2R_OUT_UVW: accumulate (v_vW[n_i] - v_vW[n_a]) (n_i - n
   __device__ void barrier_after() const {}
 };
 
-template <int L, int B, int FOUT>
+template <int L, int B, int FOUT, int NT = ARCHE_BLOCK>
 __device__ inline void z_c2r_body(const ZArgs& A, unsigned bid, cplx* lds, cplx* tw, double* sh) {
   constexpr int Nh = L / 2 + 1;
-  for (int i = threadIdx.x; i < L; i += ARCHE_BLOCK) tw[i] = A.tw[i];
+  for (int i = threadIdx.x; i < L; i += NT) tw[i] = A.tw[i];
   __syncthreads();
   const cplx* in = (const cplx*)A.in;
   const int64_t p0 = (int64_t)bid * B;
   const int nb = (int)((A.npairs - p0) < B ? (A.npairs - p0) : B);
   if constexpr (FOUT == 0) {
-    run<L, B, ARCHE_BLOCK, false, +1, 1>(HermIn{in + p0 * 2 * Nh, L, Nh, nb},
+    run<L, B, NT, false, +1, 1>(HermIn{in + p0 * 2 * Nh, L, Nh, nb},
                                           PairOut{(double*)A.out + p0 * 2 * L, L, nb, A.out_scale}, lds, tw, nb,
                                           typename Plan<L>::R{});
   } else {
     double acc = 0.0;
     const int64_t off = p0 * 2 * L;
-    run<L, B, ARCHE_BLOCK, false, +1, 1>(
+    run<L, B, NT, false, +1, 1>(
         HermIn{in + p0 * 2 * Nh, L, Nh, nb},
         PairOutUvw{A.f.n_i + off, A.f.lap_i + off, A.f.n_a + off, L, nb, A.out_scale, 0.5 * A.f.lam, &acc}, lds, tw,
         nb, typename Plan<L>::R{});

@@ -92,3 +92,5 @@ arche_status arche_k_fermi_dirac(int64_t n, const double* d_x, double* d_im12, d
 }
 
 }  // extern "C"
+
+extern "C" int32_t arche_fft_tile(int32_t pass, int32_t L, int32_t force) { return fft_tile_variant(pass, L, force); }

@@ -20,6 +20,7 @@ struct Profiler {
   size_t used = 0;
   double total_ms[PROF_KINDS] = {0, 0, 0};
   long long launches[PROF_KINDS] = {0, 0, 0};
+  unsigned mask = ~0u;  // kinds that are timed (each timed launch adds an event pair)
 
   hipEvent_t take() {
     if (used == pool.size()) {
@@ -54,6 +55,7 @@ struct ProfScope {
   int kind;
   hipStream_t s;
   ProfScope(int k, hipStream_t st) : p(g_profiler), kind(k), s(st) {
+    if (p && !((p->mask >> k) & 1u)) p = nullptr;
     if (!p) return;
     if (p->open.size() > 8192) p->collect();
     hipEvent_t a = p->take();

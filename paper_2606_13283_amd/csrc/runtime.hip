@@ -403,7 +403,7 @@ arche_status arche_scf_init(const arche_params* p, void* hip_stream, arche_ctx**
   ok = ok && dalloc(&c->spec_d, (size_t)n) == hipSuccess;
   ok = ok && dalloc(&c->sp_order, (size_t)n) == hipSuccess;
   ok = ok && dalloc(&c->sp_begin, (size_t)ns + 1) == hipSuccess;
-  c->partial_cap = (int)scf_part_offset(c) + 16 * 1024 + n + 64;
+  c->partial_cap = (int)scf_part_offset(c) + 64 * 1024 + n + 64;
   ok = ok && dalloc(&c->partials, (size_t)c->partial_cap) == hipSuccess;
   ok = ok && dalloc(&c->sums, 64) == hipSuccess;
   ok = ok && dalloc(&c->state, 1) == hipSuccess;
@@ -428,6 +428,7 @@ arche_status arche_scf_init(const arche_params* p, void* hip_stream, arche_ctx**
             hipMemcpy(c->sp_begin, begin.data(), (ns + 1) * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess;
   if (!up) return fail_init(ARCHE_EHIP, "upload failed");
   if (ionic_shells(c) != hipSuccess) return fail_init(ARCHE_ENOMEM, "shell table allocation failed");
+  if (fft_tune(&c->plan, c->ctmp, c->rtmp, c->stream) != hipSuccess) return fail_init(ARCHE_EHIP, "FFT tile tuning failed");
   *out = c;
   return ARCHE_OK;
 }
@@ -594,6 +595,7 @@ arche_status arche_profile_enable(arche_ctx* c, int32_t on) {
   if (!c) return ARCHE_EINVAL;
   if (on && !c->prof) c->prof = new (std::nothrow) Profiler();
   if (on && !c->prof) return set_err(c, ARCHE_ENOMEM, "profiler allocation failed");
+  if (on) c->prof->mask = on == 1 ? ~0u : (unsigned)on >> 1;
   if (!on) {
     delete c->prof;
     c->prof = nullptr;

@@ -24,6 +24,9 @@ __device__ inline void put_slot(double* part, int slot, unsigned nb, double v) {
 // not depend on how many blocks share the work (a batched solve, with fewer
 // blocks per snapshot, is bit-identical to an unbatched one).
 constexpr int PPT = 16;
+// More's weight may switch on once mu moves by at most this fraction of kT
+// between iterations (the chemical-potential fluctuations of Sec. 2.5.2 are small)
+constexpr double MU_SETTLED = 0.02;
 constexpr int SCF_CHUNK = ARCHE_BLOCK * PPT;
 
 __device__ inline void put_chunk(double* part, int slot, int64_t nchunk, int64_t c, double v) {
@@ -40,6 +43,91 @@ __device__ inline void put_chunk(double* part, int slot, int64_t nchunk, int64_t
 // grid_allreduce hands every block of the group the same fixed-order result, so
 // all of them take the same branches.  With CACHE (at most one chunk per block)
 // V_i and v_xc(n_i) stay in registers between the phases.
+// Phase-3 work for one chunk at chemical potential mu: n_a = c_n I_{1/2}(eta_a)
+// is stored, and the six sums of the residual and of More's weight are put in
+// slots s0..s0+5 (the last one a max).
+template <bool CACHE>
+__device__ inline void active_sums(const ActiveArgs& a, int64_t c, const double* vreg, double mu, double ikT,
+                                   const FdLds& fdl, double* sh, int s0) {
+  const bool more = a.mixing == ARCHE_MIX_MORE;
+  double sdd = 0.0, snn = 0.0, sK = 0.0, sU = 0.0, sNa = 0.0, smax = 0.0;
+  for (int q = 0; q < PPT; ++q) {
+    const int64_t i = c * SCF_CHUNK + threadIdx.x + (int64_t)ARCHE_BLOCK * q;
+    if (i < a.ng) {
+      double im, ip;
+      const double v = CACHE ? vreg[q] : a.Vi[i];
+      fd_m12_p12_lds(fdl, (mu - v) * ikT, im, ip);
+      const double na = a.cn * ip;
+      const double ni = a.n_i[i];
+      const double d = ni - na;
+      a.n_a[i] = na;
+      sdd += d * d;
+      snn += na * na;
+      if (more) {
+        // K: secant of the Thomas-Fermi potential kT eta(n) between n_a and n_i
+        const double eta_a = (mu - v) * ikT;
+        const double eta_i = fd_p12_inverse_lds(fdl, ni / a.cn, eta_a);
+        sK += a.kT * (eta_i - eta_a) * d;
+      }
+      sNa += na;
+      if (a.xc) {
+        double vi, va;
+        lda_xc(ni, vi);
+        lda_xc(na, va);
+        sU += (vi - va) * d;
+      }
+      smax = fmax(smax, fabs(d) / na);
+    }
+  }
+  const int64_t nchunk = a.nchunk;
+  double v;
+  v = block_sum(sdd, sh);
+  put_chunk(a.part, s0, nchunk, c, v);
+  v = block_sum(snn, sh);
+  put_chunk(a.part, s0 + 1, nchunk, c, v);
+  v = block_sum(sK, sh);
+  put_chunk(a.part, s0 + 2, nchunk, c, v);
+  v = block_sum(sU, sh);
+  put_chunk(a.part, s0 + 3, nchunk, c, v);
+  v = block_sum(sNa, sh);
+  put_chunk(a.part, s0 + 4, nchunk, c, v);
+  v = block_max(smax, sh);
+  put_chunk(a.part, s0 + 5, nchunk, c, v);
+}
+
+// The chunk's sums of I_{1/2} and I_{-1/2} at mu into slots s0, s0+1.
+template <bool CACHE>
+__device__ inline void newton_sums(const ActiveArgs& a, int64_t c, const double* vreg, double mu, double ikT,
+                                   const FdLds& fdl, double* sh, int s0) {
+  double s12 = 0.0, sm12 = 0.0;
+  for (int q = 0; q < PPT; ++q) {
+    const int64_t i = c * SCF_CHUNK + threadIdx.x + (int64_t)ARCHE_BLOCK * q;
+    if (i < a.ng) {
+      double im, ip;
+      const double v = CACHE ? vreg[q] : a.Vi[i];
+      fd_m12_p12_lds(fdl, (mu - v) * ikT, im, ip);
+      s12 += ip;
+      sm12 += im;
+    }
+  }
+  double b = block_sum(s12, sh);
+  put_chunk(a.part, s0, a.nchunk, c, b);
+  b = block_sum(sm12, sh);
+  put_chunk(a.part, s0 + 1, a.nchunk, c, b);
+}
+
+// Steps 1-4 of one SCF iteration for one system, run by a group of G
+// co-resident blocks (lb = this block's index in the group).
+//   1. V_i = V^ie + V_H + v_xc(n_i) + v_vW[n_i] with its sum, max and min, and
+//      the first Newton evaluation N(mu), N'(mu) at the previous iteration's mu
+//   2. Newton search of mu (safeguarded by bisection): N(mu) = N_e
+//   3. n_a at mu with the sums of the residual and of More's weight; a Newton
+//      pass that follows a small residual |N - N_e| forms them too, so when it
+//      converges no separate pass is needed
+//   4. the SCF scalars (block 0)
+// grid_allreduce hands every block of the group the same fixed-order result, so
+// all of them take the same branches.  With CACHE (at most one chunk per block)
+// V_i stays in registers between the phases.
 template <bool CACHE>
 __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigned G, const FdLds& fdl, double* sh,
                                        double* r) {
@@ -48,11 +136,15 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
   unsigned epoch = (unsigned)(st->iter + 1) * 256u;  // grows by one per all-reduce; disjoint per launch
   const int64_t nchunk = a.nchunk;
   double vreg[CACHE ? PPT : 1];
+  const double kT = a.kT;
+  const double ikT = 1.0 / kT;
+  const double mu_prev = st->mu;  // NaN on the first iteration
+  const bool try_prev = mu_prev == mu_prev;
   // with CACHE each block owns at most one chunk (lb), otherwise chunks lb, lb+G, ...
 #define FOR_CHUNKS(c)                                           \
   for (int64_t c = lb; c < nchunk; c += (CACHE ? nchunk : G))
 
-  // 1. potential assembly
+  // 1. potential assembly (+ N, N' at the previous mu)
   FOR_CHUNKS(c) {
     double vmin = INFINITY, vmax = -INFINITY, vsum = 0.0;
     for (int q = 0; q < PPT; ++q) {
@@ -79,46 +171,49 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
     put_chunk(a.part, 1, nchunk, c, v);
     v = block_max(-vmin, sh);
     put_chunk(a.part, 2, nchunk, c, v);
+    if (try_prev) newton_sums<CACHE>(a, c, vreg, mu_prev, ikT, fdl, sh, 3);
   }
-  grid_allreduce(a.part, nchunk, a.res, 0, 3, 0x6u, G, lb, a.flags, go, ++epoch, a.err, r, sh);
+  grid_allreduce(a.part, nchunk, a.res, 0, try_prev ? 5 : 3, 0x6u, G, lb, a.flags, go, ++epoch, a.err, r, sh);
   const double Vsum = r[0], Vmax = r[1], Vmin = -r[2];
-  const double kT = a.kT;
-  const double ikT = 1.0 / kT;
+  const double pre12 = r[3], pre_m12 = r[4];
   double lo = Vmin + kT * a.eta0;
   double hi = Vmax + kT * a.eta0;
-  double mu = st->mu;
-  if (!(lo <= mu && mu <= hi)) mu = Vsum / (double)a.ng + kT * a.eta0;
+  double mu = mu_prev;
+  const bool use_prev = try_prev && lo <= mu && mu <= hi;
+  if (!use_prev) mu = Vsum / (double)a.ng + kT * a.eta0;
 
   // 2. Newton search of mu
   int it;
-  bool found = false;
-  double N = 0.0, dN = 0.0;
+  bool found = false, have_sums = false;
+  double N = 0.0, dN = 0.0, fprev = INFINITY;
+  double D[6] = {0, 0, 0, 0, 0, 0};
   for (it = 1; it <= a.max_newton; ++it) {
-    FOR_CHUNKS(c) {
-      double s12 = 0.0, sm12 = 0.0;
-      for (int q = 0; q < PPT; ++q) {
-        const int64_t i = c * SCF_CHUNK + threadIdx.x + (int64_t)ARCHE_BLOCK * q;
-        if (i < a.ng) {
-          double im, ip;
-          const double v = CACHE ? vreg[q] : a.Vi[i];
-          fd_m12_p12_lds(fdl, (mu - v) * ikT, im, ip);
-          s12 += ip;
-          sm12 += im;
-        }
+    bool spec = false;
+    if (it == 1 && use_prev) {
+      N = a.dv * a.cn * pre12;
+      dN = a.dv * a.cn * 0.5 * ikT * pre_m12;
+    } else {
+      // quadratic convergence: after |N - N_e| <= 1e-7 N_e this pass is most likely the last
+      spec = fabs(fprev) <= 1e-7 * a.Ne;
+      FOR_CHUNKS(c) {
+        newton_sums<CACHE>(a, c, vreg, mu, ikT, fdl, sh, 0);
+        if (spec) active_sums<CACHE>(a, c, vreg, mu, ikT, fdl, sh, 2);
       }
-      double b = block_sum(s12, sh);
-      put_chunk(a.part, 3, nchunk, c, b);
-      b = block_sum(sm12, sh);
-      put_chunk(a.part, 4, nchunk, c, b);
+      grid_allreduce(a.part, nchunk, a.res, 0, spec ? 8 : 2, spec ? 0x80u : 0u, G, lb, a.flags, go, ++epoch, a.err,
+                     r, sh);
+      N = a.dv * a.cn * r[0];
+      dN = a.dv * a.cn * 0.5 * ikT * r[1];
     }
-    grid_allreduce(a.part, nchunk, a.res, 3, 2, 0u, G, lb, a.flags, go, ++epoch, a.err, r, sh);
-    N = a.dv * a.cn * r[0];
-    dN = a.dv * a.cn * 0.5 * ikT * r[1];
     const double f = N - a.Ne;
     if (fabs(f) <= 1e-14 * a.Ne) {
       found = true;
+      if (spec) {
+        have_sums = true;
+        for (int k = 0; k < 6; ++k) D[k] = r[2 + k];
+      }
       break;
     }
+    fprev = f;
     if (f > 0.0)
       hi = mu;
     else
@@ -134,57 +229,22 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
   }
   if (it > a.max_newton) it = a.max_newton;
 
-  // 3. active density and the mixing reductions
-  const double cchi = a.cn * 0.5 * ikT;
-  FOR_CHUNKS(c) {
-    double sdd = 0.0, snn = 0.0, sK = 0.0, sU = 0.0, sNa = 0.0, smax = 0.0;
-    for (int q = 0; q < PPT; ++q) {
-      const int64_t i = c * SCF_CHUNK + threadIdx.x + (int64_t)ARCHE_BLOCK * q;
-      if (i < a.ng) {
-        double im, ip;
-        const double v = CACHE ? vreg[q] : a.Vi[i];
-        fd_m12_p12_lds(fdl, (mu - v) * ikT, im, ip);
-        const double na = a.cn * ip;
-        const double chi = cchi * im;
-        const double ni = a.n_i[i];
-        const double d = ni - na;
-        a.n_a[i] = na;
-        sdd += d * d;
-        snn += na * na;
-        sK += d * d / chi;
-        sNa += na;
-        if (a.xc) {
-          double vi, va;
-          lda_xc(ni, vi);
-          lda_xc(na, va);
-          sU += (vi - va) * d;
-        }
-        smax = fmax(smax, fabs(d) / na);
-      }
-    }
-    double v;
-    v = block_sum(sdd, sh);
-    put_chunk(a.part, 5, nchunk, c, v);
-    v = block_sum(snn, sh);
-    put_chunk(a.part, 6, nchunk, c, v);
-    v = block_sum(sK, sh);
-    put_chunk(a.part, 7, nchunk, c, v);
-    v = block_sum(sU, sh);
-    put_chunk(a.part, 8, nchunk, c, v);
-    v = block_sum(sNa, sh);
-    put_chunk(a.part, 9, nchunk, c, v);
-    v = block_max(smax, sh);
-    put_chunk(a.part, 10, nchunk, c, v);
+  // 3. active density and the mixing reductions (unless the last Newton pass formed them)
+  if (!have_sums) {
+    FOR_CHUNKS(c) active_sums<CACHE>(a, c, vreg, mu, ikT, fdl, sh, 0);
+    grid_allreduce(a.part, nchunk, a.res, 0, 6, 0x20u, G, lb, a.flags, go, ++epoch, a.err, r, sh);
+    for (int k = 0; k < 6; ++k) D[k] = r[k];
   }
 #undef FOR_CHUNKS
-  grid_allreduce(a.part, nchunk, a.res, 5, 6, 0x20u, G, lb, a.flags, go, ++epoch, a.err, r, sh);
-  const double DD = r[0], NN = r[1], KK = r[2], UU = r[3], NA = r[4], MX = r[5];
+  const double DD = D[0], NN = D[1], KK = D[2], UU = D[3], NA = D[4], MX = D[5];
 
   if (lb == 0 && threadIdx.x == 0) {
     const double res = sqrt(DD / NN);
     const int t = st->iter;
     int more = st->more_on;
-    if (a.mixing == ARCHE_MIX_MORE && !more && t >= a.warmup && MX <= a.trust) more = 1;
+    if (a.mixing == ARCHE_MIX_MORE && !more && t >= a.warmup &&
+        (MX <= a.trust || fabs(mu - mu_prev) <= MU_SETTLED * kT))
+      more = 1;
     st->mu = mu;
     st->N = N;
     st->dN = dN;

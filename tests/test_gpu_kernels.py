@@ -65,6 +65,26 @@ def test_fft_roundtrip_vs_numpy(torch_cuda, shape):
     assert np.max(np.abs(y - yref)) <= 5e-14 * np.max(np.abs(yref)) * math.log2(np.prod(shape))
 
 
+@pytest.mark.parametrize("var", [1, 2, 0])
+def test_fft_tile_variants(torch_cuda, var):
+    """Every tile variant of the tunable line lengths is the same transform."""
+    torch = torch_cuda
+    L = arche.load()
+    shape = (100, 120, 128)
+    for pas, n in ((0, shape[1]), (1, shape[0]), (2, shape[2])):
+        assert L.arche_fft_tile(pas, n, var) == var
+    say("fft tile variant", var, shape)
+    rng = np.random.default_rng(var)
+    f = rng.standard_normal(shape)
+    X = arche.fft_r2c(torch.from_numpy(f).cuda()).cpu().numpy()
+    ref = np.fft.rfftn(f)
+    assert np.max(np.abs(X - ref)) <= 5e-14 * np.max(np.abs(ref)) * math.log2(np.prod(shape))
+    H = rng.standard_normal(ref.shape) + 1j * rng.standard_normal(ref.shape)
+    y = arche.fft_c2r(torch.from_numpy(H).cuda(), shape[2]).cpu().numpy()
+    yref = np.fft.irfftn(H, s=shape, axes=(0, 1, 2)) * np.prod(shape)
+    assert np.max(np.abs(y - yref)) <= 5e-14 * np.max(np.abs(yref)) * math.log2(np.prod(shape))
+
+
 def _ctx_and_oracle(w, opts=None):
     ctx = arche.Context.from_workload(w, opts)
     s = oscf.System(w.cell, w.grid, w.pos, w.species, w.Z, w.rc, w.mass, w.kT, w.lam, w.xc)

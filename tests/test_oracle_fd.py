@@ -134,3 +134,37 @@ def test_free_energy_density_derivative():
             fp = fd.free_energy_density0(np.array([ep]), kT)[0]
             fm = fd.free_energy_density0(np.array([em]), kT)[0]
             assert abs((fp - fm) / (2 * h * nn) - kT * e) <= 1e-7 * max(1.0, abs(kT * e))
+
+
+def test_inverse_array_round_trip_and_scalar_agreement():
+    y = np.logspace(-30, 6, 73)
+    x = fd.I_p12_inverse_array(y)
+    back = fd.I_p12(x)
+    assert np.max(np.abs(back - y) / y) <= 1e-13
+    for k in (0, 20, 40, 60, 72):
+        assert abs(x[k] - fd.I_p12_inverse(float(y[k]))) <= 1e-12 * max(1.0, abs(x[k]))
+    # the brackets hold the root, and a start anywhere converges to the same X
+    lo = np.log(y / math.gamma(1.5))
+    hi = np.maximum((1.5 * y) ** (2.0 / 3.0), lo + 1.0) + 1.0
+    assert np.all(fd.I_p12(lo - 1e-9) < y) and np.all(fd.I_p12(hi) > y)
+    x2 = fd.I_p12_inverse_array(y, x + np.linspace(-30.0, 30.0, y.size))
+    assert np.max(np.abs(x2 - x) / np.maximum(1.0, np.abs(x))) <= 1e-14
+
+
+def test_secant_K_reduces_to_the_second_order_form():
+    """K = int kT (eta(n_i) - eta_a) dn equals int dn^2 / (dn_a/dmu) to second order in dn."""
+    rng = np.random.default_rng(3)
+    kT = 0.2
+    cn = fd.c_n(kT)
+    eta_a = rng.uniform(-5.0, 20.0, 400)
+    n_a = cn * fd.I_p12(eta_a)
+    chi = cn / (2.0 * kT) * fd.I_m12(eta_a)
+    shape = rng.normal(size=400)
+    ratios = []
+    for eps in (1e-2, 1e-3, 1e-4):
+        dn = eps * n_a * shape
+        eta_i = fd.I_p12_inverse_array((n_a + dn) / cn)
+        Ks = np.sum(kT * (eta_i - eta_a) * dn)
+        Kc = np.sum(dn * dn / chi)
+        ratios.append(abs(Ks / Kc - 1.0))
+    assert ratios[0] < 0.05 and ratios[1] < ratios[0] / 5 and ratios[2] < ratios[1] / 5
