@@ -3,7 +3,7 @@
  * on the periodic grid that corrects the one-center guess (Sec. 2.5.1) from
  * [one-center guess g, previous converged density p].  With a = g/n0 - 1 and
  * b = p/n0 - 1 (n0 = N_e/|Omega|) the network returns r and proposes
- * n = n0 (1 + a + r) = g + n0 r.
+ * n = n0 (1 + a + r) = g + n0 r, kept at or above 0.1 g.
  *
  * Network: 1x1x1 input layer 2->32 + ReLU; four levels of width 32, each two
  * periodic 3x3x3 convolutions + ReLU (encoder), 2x2x2 mean pooling between
@@ -57,7 +57,8 @@ arche_status arche_net_get_params(arche_net *net, float *params_host, int64_t n)
 arche_status arche_net_forward(arche_net *net, const double *guess_dev, const double *prev_dev, double n0,
                                double *r_out_dev);
 
-/* n_out_dev = guess + n0 r (not floored). Asynchronous. */
+/* n_out_dev = max(guess + n0 r, 0.1 guess) pointwise (the correction may not
+ * empty a region; not renormalised).  Asynchronous. */
 arche_status arche_net_propose(arche_net *net, const double *guess_dev, const double *prev_dev, double n0,
                                double *n_out_dev);
 

@@ -28,17 +28,25 @@ One iteration, with input density n_i (Sec. 2.5 and its subsections):
      iteration t >= warmup at which either the second-order expansion behind
      the weight holds pointwise, max_r |Delta n| / n_a <= more_trust (0.5), or
      mu moved by at most MU_SETTLED kT since the previous iteration, and is
-     never undone.
+     never undone; and the weight may fall by at most W_MAX_DROP (0.05) per
+     iteration (where xc makes U small or negative in low-density regions the
+     quadratic model sends w to 0 in one step and the iteration diverges).
   6. n_o = n_a + w Delta n becomes the next n_i.
 
 Initial densities (Sec. 2.5 and 2.5.1):
   uniform     n_0 = N_e / |Omega|
   one-center  g^ = n^ / S_Z taken as a least-squares fit per |k|^2 shell
               (g^(shell) = sum Re(n^ conj S_Z) / sum |S_Z|^2 over the shell),
-              n^_i = g^ S_Z(new positions), floored at 1e-12 n_0 and rescaled
-              to N_e; falls back to uniform if the floor added more than 1e-6
-              of the charge.  Shells whose sum |S_Z|^2 is below 1e-12 x
-              (shell size) x sum_j Z_j^2 get g^ = 0.
+              n^_i = g^ S_Z(new positions), floored at GUESS_FLOOR n_0 and
+              rescaled to N_e; falls back to uniform if the floor added more
+              than MAX_FLOOR_CHARGE of the charge.  (The superposition rings
+              slightly negative between the ions; a floor near zero would make
+              sqrt(n), and with it the von Weizsaecker potential of the guess,
+              nearly singular there.)  Shells whose sum |S_Z|^2 is below SHELL_CUT x
+              (shell size) x sum_j Z_j^2 get g^ = 0: near a perfect lattice
+              S_Z is tiny off the lattice's own shells, and n^ / S_Z there is
+              the nonlinear response, not a one-center profile (random
+              positions give sum |S_Z|^2 ~ (shell size) x sum Z_j^2).
 """
 from __future__ import annotations
 
@@ -52,7 +60,11 @@ from . import functional as fn
 from . import ionic
 from .grid import Grid
 
-RESIDUAL_FLOOR = 1e-12  # floor of the one-center guess, in units of n_0
+GUESS_FLOOR = 1e-3  # floor of the one-center guess, in units of n_0
+MAX_FLOOR_CHARGE = 1e-2  # uniform instead when the floor adds more than this fraction of N_e
+SHELL_CUT = 1e-4  # shells with less structure-factor weight get no one-center profile
+# More's weight may fall by at most this much from one iteration to the next
+W_MAX_DROP = 0.05
 
 
 @dataclass
@@ -176,7 +188,7 @@ def one_center_profile(sys: System, nhat_prev: np.ndarray, SZ_prev: np.ndarray):
     snum = np.bincount(inv, weights=num, minlength=uk.size)
     sden = np.bincount(inv, weights=den, minlength=uk.size)
     cnt = np.bincount(inv, minlength=uk.size)
-    thresh = 1e-12 * cnt * float(np.sum(sys.Zj ** 2))
+    thresh = SHELL_CUT * cnt * float(np.sum(sys.Zj ** 2))
     gsh = np.where(sden > thresh, snum / np.where(sden > 0, sden, 1.0), 0.0)
     return gsh[inv].reshape(g.shape)
 
@@ -192,9 +204,9 @@ def initial_density(sys: System, ion: Ionic, kind="uniform", prev=None):
         ghat = one_center_profile(sys, nhat_prev, SZ_prev)
         n = g.inverse(ghat * ion.SZ)
         raw = g.integrate(n)
-        n = np.maximum(n, RESIDUAL_FLOOR * n0)
+        n = np.maximum(n, GUESS_FLOOR * n0)
         added = g.integrate(n) - raw
-        if abs(added) > 1e-6 * sys.Ne:
+        if abs(added) > MAX_FLOOR_CHARGE * sys.Ne:
             return np.full(g.shape, n0), True
         n = n * (sys.Ne / g.integrate(n))
         return n, False
@@ -257,6 +269,8 @@ def scf(sys: System, ion: Ionic, n_init: np.ndarray, mixing="more", tol=1e-10, m
             eta_i = fd.I_p12_inverse_array(n_i / cn, eta)
             K = g.integrate(sys.kT * (eta_i - eta) * dn)
             w = min(max(U / (U + K), 0.0), 0.995)
+            if ws:
+                w = max(w, ws[-1] - W_MAX_DROP)
         else:
             w = w_fixed
         ws.append(w)

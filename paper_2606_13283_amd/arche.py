@@ -148,6 +148,8 @@ def load(path: str = LIB_PATH):
     L.arche_net_free.restype = None
     L.arche_set_init_net.argtypes = [vp, vp]
     L.arche_set_init_net.restype = st
+    L.arche_debug_history.argtypes = [vp, _dp, ctypes.c_int32, _ip]
+    L.arche_debug_history.restype = st
     L.arche_fft_tile.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     L.arche_fft_tile.restype = ctypes.c_int32
     L.arche_k_fft_r2c.argtypes = [_ip, vp, vp, vp]
@@ -289,6 +291,16 @@ class Context:
         else:
             out = np.empty(self.grid)
         self._check(self._L.arche_debug_get(self._h, w, _ptr(out)))
+        return out
+
+    def history(self):
+        """Per-iteration rows of the last solve: iteration, residual, w, mu, K, U,
+        max |dn|/n_a, Newton passes, More on, error."""
+        n = ctypes.c_int32(0)
+        self._check(self._L.arche_debug_history(self._h, None, 0, ctypes.byref(n)))
+        out = np.zeros((n.value, 10))
+        if n.value:
+            self._check(self._L.arche_debug_history(self._h, _ptr(out), n.value, ctypes.byref(n)))
         return out
 
     def one_center_guess(self, pos):

@@ -172,6 +172,7 @@ struct arche_ctx {
   ActiveArgs active{};
   std::vector<IterStep> steps;
   arche_net* init_net = nullptr;  // learned initial density (not owned)
+  std::vector<ScfState> hist;     // polled SCF states of the last single solve
 };
 
 // device Fermi-Dirac tables (uploaded once per process and device)

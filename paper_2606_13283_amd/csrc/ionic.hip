@@ -305,6 +305,12 @@ k_pressure_ie(const cplx* nhat, const cplx* Sp, const cplx* Sm, SpeciesInfo sp, 
   if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
 
+// Shells whose sum |S_Z|^2 is below SHELL_CUT x (shell size) x sum_j Z_j^2 get no
+// one-center profile: near a perfect lattice S_Z is tiny off the lattice's own
+// shells and n^/S_Z there is the nonlinear response (random positions give
+// sum |S_Z|^2 ~ (shell size) x sum Z_j^2).
+constexpr double SHELL_CUT = 1e-4;
+
 // one-center profile per shell: g = sum Re(n^ conj SZ) / sum |SZ|^2 over the full box
 __global__ void __launch_bounds__(ARCHE_BLOCK)
 k_shell_profile(const cplx* nhat, const cplx* SZp, const cplx* SZm, const int* perm, const int* off, int nshell,
@@ -327,7 +333,7 @@ k_shell_profile(const cplx* nhat, const cplx* SZp, const cplx* SZm, const int* p
       cnt += 1.0;
     }
   }
-  gsh[s] = den > 1e-12 * cnt * sumZ2 ? num / den : 0.0;
+  gsh[s] = den > SHELL_CUT * cnt * sumZ2 ? num / den : 0.0;
 }
 
 // n^_i(m) = g(shell(m)) (SZ+(m) + SZ-(m))/2
@@ -499,17 +505,18 @@ hipError_t ionic_shells(arche_ctx* c) {
   return hipSuccess;
 }
 
-// One-center initial density (Sec. 2.5.1) from the previous converged step:
-// g per shell, n^_i = g (SZ+ + SZ-)/2 at the new positions, C2R, floor at
-// 1e-12 n_0 and rescale to N_e; uniform if the floor added more than 1e-6 N_e.
-// Floor n at 1e-12 n0 and rescale it to N_e electrons; *ok = false (n left
-// floored, not rescaled) when the floor changed the charge beyond rounding or
-// the result is not finite.
+// Floor n at GUESS_FLOOR n_0 and rescale it to N_e electrons; *ok = false (n
+// left floored, not rescaled) when the floor added more than MAX_FLOOR_CHARGE
+// of the charge (the guess is then too poor to use) or the result is not
+// finite.  A guess rings slightly negative between the ions; a floor near zero
+// would make sqrt(n), and the von Weizsaecker potential, nearly singular there.
+constexpr double GUESS_FLOOR = 1e-3;
+constexpr double MAX_FLOOR_CHARGE = 1e-2;
 hipError_t scf_floor_renorm(arche_ctx* c, double* n, bool* ok) {
   const GridInfo& g = c->g;
   const double n0 = c->Ne / g.vol;
   const int nb = red_blocks(g.ng);
-  hipLaunchKernelGGL(k_floor, dim3(nb), dim3(ARCHE_BLOCK), 0, c->stream, n, g.ng, 1e-12 * n0, c->partials);
+  hipLaunchKernelGGL(k_floor, dim3(nb), dim3(ARCHE_BLOCK), 0, c->stream, n, g.ng, GUESS_FLOOR * n0, c->partials);
   HIP_TRY(hipGetLastError());
   HIP_TRY(finish_sums(c->partials, nb, 1, c->sums, c->stream));
   HIP_TRY(finish_sums(c->partials + nb, nb, 1, c->sums + 1, c->stream));
@@ -517,13 +524,15 @@ hipError_t scf_floor_renorm(arche_ctx* c, double* n, bool* ok) {
   HIP_TRY(hipMemcpyAsync(h, c->sums, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   const double raw = g.dv * h[0], fl = g.dv * h[1];
-  *ok = std::fabs(fl - raw) <= 1e-6 * c->Ne && fl > 0.0 && std::isfinite(fl);
+  *ok = std::fabs(fl - raw) <= MAX_FLOOR_CHARGE * c->Ne && fl > 0.0 && std::isfinite(fl);
   if (!*ok) return hipSuccess;
   hipLaunchKernelGGL(k_scale, dim3(grid_for(g.ng)), dim3(ARCHE_BLOCK), 0, c->stream, n, g.ng, c->Ne / fl);
   return hipGetLastError();
 }
 
-// n_i = the one-center guess (Sec. 2.5.1), without the derived fields
+// n_i = the one-center guess (Sec. 2.5.1) from the previous converged step
+// (g per shell, n^_i = g (SZ+ + SZ-)/2 at the new positions, C2R), floored and
+// rescaled; uniform when scf_floor_renorm rejects it.  No derived fields.
 hipError_t scf_one_center_density(arche_ctx* c, int* used_fallback) {
   const GridInfo& g = c->g;
   *used_fallback = 0;

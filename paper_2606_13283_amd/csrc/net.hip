@@ -439,11 +439,15 @@ k_adam(float* __restrict__ prm, const float* __restrict__ grad, float* __restric
   }
 }
 
-// proposal n = n0 (1 + a + r), a = g/n0 - 1
+// proposal n = n0 (1 + a + r) = g + n0 r (a = g/n0 - 1), kept at or above
+// PROPOSAL_FLOOR g: the network corrects the guess, it does not empty a region
+constexpr double PROPOSAL_FLOOR = 0.1;
 __global__ void __launch_bounds__(256)
 k_propose(const double* __restrict__ guess, const double* __restrict__ r, double n0, double* __restrict__ n, int64_t P) {
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x)
-    n[p] = guess[p] + n0 * r[p];
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
+    const double g = guess[p], rp = r[p];
+    n[p] = rp == rp ? fmax(g + n0 * rp, PROPOSAL_FLOOR * g) : rp;  // a NaN stays visible
+  }
 }
 
 unsigned grid1(int64_t n) {

@@ -142,8 +142,10 @@ arche_status collect_state(arche_ctx* c, arche_result* out) {
 }
 
 // SCF loop: one queued iteration ahead of the convergence poll.  The state was
-// reset by begin_solve; the last iteration raises done by itself.
+// reset by begin_solve; the last iteration raises done by itself.  The polled
+// states are kept as the solve's convergence history.
 arche_status run_scf(arche_ctx* c, arche_result* out) {
+  c->hist.clear();
   hipEvent_t ev[2];
   CK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
   CK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
@@ -156,7 +158,10 @@ arche_status run_scf(arche_ctx* c, arche_result* out) {
     if (e == hipSuccess) e = hipEventRecord(ev[t & 1], c->stream);
     if (e == hipSuccess && t >= 1) {
       e = hipEventSynchronize(ev[(t - 1) & 1]);
-      if (e == hipSuccess && ring[(t - 1) & 1].done) stop = true;
+      if (e == hipSuccess) {
+        c->hist.push_back(ring[(t - 1) & 1]);
+        if (ring[(t - 1) & 1].done) stop = true;
+      }
     }
     if (e != hipSuccess) {
       (void)hipEventDestroy(ev[0]);
@@ -588,6 +593,28 @@ arche_status arche_debug_one_center(arche_ctx* c, const double* pos_host, double
   CK(hipStreamSynchronize(c->stream));
   c->solved = false;
   c->converged = false;
+  return ARCHE_OK;
+}
+
+arche_status arche_debug_history(arche_ctx* c, double* rows_host, int32_t max_rows, int32_t* n_rows) {
+  if (!c || !n_rows) return ARCHE_EINVAL;
+  const int n = (int)c->hist.size();
+  *n_rows = n;
+  if (!rows_host) return ARCHE_OK;
+  for (int i = 0; i < n && i < max_rows; ++i) {
+    const ScfState& s = c->hist[i];
+    double* r = rows_host + 10 * (size_t)i;
+    r[0] = s.iter;
+    r[1] = s.res;
+    r[2] = s.w;
+    r[3] = s.mu;
+    r[4] = s.K;
+    r[5] = s.UH + s.Uxc + s.Uvw;
+    r[6] = s.maxrel;
+    r[7] = s.newton_last;
+    r[8] = s.more_on;
+    r[9] = s.err;
+  }
   return ARCHE_OK;
 }
 

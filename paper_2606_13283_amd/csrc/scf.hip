@@ -27,6 +27,9 @@ constexpr int PPT = 16;
 // More's weight may switch on once mu moves by at most this fraction of kT
 // between iterations (the chemical-potential fluctuations of Sec. 2.5.2 are small)
 constexpr double MU_SETTLED = 0.02;
+// More's weight may fall by at most this much from one iteration to the next
+// (the quadratic model can send it to 0 in one step in low-density regions)
+constexpr double W_MAX_DROP = 0.05;
 constexpr int SCF_CHUNK = ARCHE_BLOCK * PPT;
 
 __device__ inline void put_chunk(double* part, int slot, int64_t nchunk, int64_t c, double v) {
@@ -66,7 +69,7 @@ __device__ inline void active_sums(const ActiveArgs& a, int64_t c, const double*
       if (more) {
         // K: secant of the Thomas-Fermi potential kT eta(n) between n_a and n_i
         const double eta_a = (mu - v) * ikT;
-        const double eta_i = fd_p12_inverse_lds(fdl, ni / a.cn, eta_a);
+        const double eta_i = fd_p12_inverse_from(fdl, ni / a.cn, eta_a, ip, im);
         sK += a.kT * (eta_i - eta_a) * d;
       }
       sNa += na;
@@ -344,7 +347,8 @@ k_uh_partial(const ScfState* st, const cplx* nhat_i, const cplx* nhat_a, GridInf
 }
 
 // Mixing weight (Sec. 2.5.2): w = U/(U+K) with U = U_H + U_xc + U_vW once the More
-// weight is on, else w_fixed; clamped to [0, 0.995].  One block per system.
+// weight is on, else w_fixed; clamped to [0, 0.995] and to at most W_MAX_DROP
+// below the previous weight.  One block per system.
 __device__ inline void mix_weight_body(const MixWeightArgs& m, double* sh) {
   ScfState* st = m.st;
   if (st->done) return;
@@ -362,6 +366,8 @@ __device__ inline void mix_weight_body(const MixWeightArgs& m, double* sh) {
       const double U = st->UH + st->Uxc + st->Uvw;
       w = U / (U + st->K);
       w = fmin(fmax(w, 0.0), 0.995);
+      // at most W_MAX_DROP below the previous weight (st->w)
+      w = fmax(w, st->w - W_MAX_DROP);
       if (!(w == w)) w = m.w_fixed;
     }
     st->w = w;

@@ -66,7 +66,7 @@ def test_learned_guess_saves_iterations(trained):
 def test_unusable_proposal_falls_back():
     net = arche.Net((64, 64, 64))
     p = LN.init_params(1)
-    p[-1] = -10.0  # out.b: proposal n = g - 10 n0, negative everywhere
+    p[-1] = np.nan  # out.b: a non-finite proposal
     net.set_params(p)
     w = W.fcc256_at(5.0, seed=301)
     tr = LN.Trajectory(w, init=arche.INIT_LEARNED, net=net)
