@@ -140,7 +140,7 @@ def test_one_center_exact_for_single_atom():
     g = Grid((9.0, 9.0, 9.0), (24, 24, 24))
     s = scf.System(g.cell, g.shape, np.array([[1.0, 2.0, 3.0]]), np.zeros(1, int), (3.0,), (1.1,),
                    (1.0,), W.ev(10.0), 0.2, True)
-    sigma = 0.9
+    sigma = 2.5  # wide enough that the guess floor (1e-3 n0) never binds
     def gauss_hat(r0):
         kr = g.k[0] * r0[0] + g.k[1] * r0[1] + g.k[2] * r0[2]
         return 3.0 * np.exp(-2 * math.pi ** 2 * sigma ** 2 * g.k2) * np.exp(-2j * math.pi * kr)
@@ -151,4 +151,5 @@ def test_one_center_exact_for_single_atom():
     n1, fb = scf.initial_density(s.with_positions(r1[None]), ion1, "one_center", (gauss_hat(r0), 3.0 * S0[0]))
     assert not fb
     ref = g.inverse(gauss_hat(r1))
+    assert np.min(ref) > 2 * scf.GUESS_FLOOR * s.Ne / g.volume
     assert np.max(np.abs(n1 - ref)) <= 1e-12 * np.max(ref)
