@@ -52,6 +52,11 @@ arche_status arche_debug_get(arche_ctx *ctx, int32_t which, double *dst_host);
  * solve starts afresh (the guess is not kept as a solved state). */
 arche_status arche_debug_one_center(arche_ctx *ctx, const double *pos_host, double *n_init_host,
                                     int32_t *used_fallback);
+/* As arche_debug_one_center, and raw_host (may be NULL) [Nx][Ny][Nz] receives
+ * the learned proposal's guide G = n0 + the one-center superposition's change
+ * from the previous to the new positions (arche_net.h). */
+arche_status arche_debug_one_center2(arche_ctx *ctx, const double *pos_host, double *n_init_host,
+                                     int32_t *used_fallback, double *raw_host);
 
 /* Per-kernel timing.  When enabled, every launch of the kernels below made by
  * calls on ctx is bracketed by a pair of hipEvents on the context's stream and

@@ -1,9 +1,14 @@
 /*
- * arche_net.h -- learned initial density for the SCF of arche.h: a 3D U-Net
- * on the periodic grid that corrects the one-center guess (Sec. 2.5.1) from
- * [one-center guess g, previous converged density p].  With a = g/n0 - 1 and
- * b = p/n0 - 1 (n0 = N_e/|Omega|) the network returns r and proposes
- * n = n0 (1 + a + r) = g + n0 r, kept at or above 0.1 g.
+ * arche_net.h -- learned initial density for the SCF of arche.h, replacing the
+ * one-center guess (Sec. 2.5.1): a 3D U-Net on the periodic grid.  Inputs: the
+ * guide G = n0 + the one-center superposition's change between the previous
+ * and the new positions, g^ (S_Z(new) - S_Z(old)) in real space, and the
+ * previous converged density p.  With a = G/n0 - 1 and b = p/n0 - 1
+ * (n0 = N_e/|Omega|) the network returns r, the predicted change n/n0 - 1 - b
+ * of the converged density.  In an SCF solve the proposal is
+ * n = p + n0 LP(r), LP a low pass exp(-(|k|/k_c)^2) with k_c a quarter of the
+ * smallest Nyquist frequency (short-wavelength error in a guess slows the SCF
+ * down), kept at or above 0.1 p and renormalised.
  *
  * Network: 1x1x1 input layer 2->32 + ReLU; four levels of width 32, each two
  * periodic 3x3x3 convolutions + ReLU (encoder), 2x2x2 mean pooling between
@@ -57,12 +62,12 @@ arche_status arche_net_get_params(arche_net *net, float *params_host, int64_t n)
 arche_status arche_net_forward(arche_net *net, const double *guess_dev, const double *prev_dev, double n0,
                                double *r_out_dev);
 
-/* n_out_dev = max(guess + n0 r, 0.1 guess) pointwise (the correction may not
- * empty a region; not renormalised).  Asynchronous. */
+/* n_out_dev = max(prev + n0 r, 0.1 prev) pointwise (no low pass, not
+ * renormalised).  Asynchronous. */
 arche_status arche_net_propose(arche_net *net, const double *guess_dev, const double *prev_dev, double n0,
                                double *n_out_dev);
 
-/* Loss L = mean over the grid of (r - r*)^2 with r* = conv/n0 - 1 - a, and its
+/* Loss L = mean over the grid of (r - r*)^2 with r* = conv/n0 - 1 - b, and its
  * gradient with respect to every parameter (kept in the net, replacing the
  * previous one; read with arche_net_get_grads).  Synchronous; *loss_out may be
  * NULL. */
@@ -89,11 +94,11 @@ void arche_net_free(arche_net *net);
 
 /* Use `net` (same grid as the context; may be NULL to detach) for solves with
  * p.init == ARCHE_INIT_LEARNED: after a converged step the guess is the net's
- * proposal from the one-center guess and the previous converged density,
- * floored and renormalised to N_e; before any converged step, or when the
- * proposal has negative mass beyond rounding or is not finite, the one-center
- * (or uniform) guess is used and arche_result.used_fallback is set.  The
- * context does not own the net. */
+ * proposal from G and the previous converged density, floored and
+ * renormalised to N_e; before any converged
+ * step, or when the proposal is not finite, the plain guess (one-center, or
+ * uniform when that rings negative) is used and arche_result.used_fallback is
+ * set.  The context does not own the net. */
 arche_status arche_set_init_net(arche_ctx *ctx, arche_net *net);
 
 #ifdef __cplusplus

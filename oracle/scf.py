@@ -61,8 +61,8 @@ from . import ionic
 from .grid import Grid
 
 GUESS_FLOOR = 1e-3  # floor of the one-center guess, in units of n_0
-MAX_FLOOR_CHARGE = 1e-2  # uniform instead when the floor adds more than this fraction of N_e
-SHELL_CUT = 1e-4  # shells with less structure-factor weight get no one-center profile
+MAX_FLOOR_CHARGE = 1e-6  # uniform instead when the floor adds more than this fraction of N_e
+SHELL_CUT = 1e-12  # shells with less structure-factor weight get no one-center profile
 # More's weight may fall by at most this much from one iteration to the next
 W_MAX_DROP = 0.05
 

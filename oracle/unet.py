@@ -4,22 +4,29 @@ against.  Only tests may import it.
 
 The paper's initial densities (Sec. 2.5, 2.5.1) are the uniform one and the
 one-center profile; the learned proposal is an addition that replaces the
-one-center guess by a network's correction of it.  The network is a 3D U-Net
-on the periodic grid, constant width 32 on four levels:
+one-center guess: the previous converged density p moved by the change the
+network predicts from p and from the one-center superposition's own change
+between the old and the new positions.  The network is a 3D U-Net on the periodic
+grid, constant width 32 on four levels:
 
-  x = [a, b] with a = g/n0 - 1 (one-center guess g), b = p/n0 - 1 (previous
-      converged density p), n0 = N_e/|Omega|
+  x = [a, b] with a = G/n0 - 1 (G = n0 + the superposition's change
+      g^ (S_Z(new) - S_Z(old)) transformed to real space), b = p/n0 - 1,
+      n0 = N_e/|Omega|
   h = relu(conv1(x; 2->32))
   s0 = E0(h)                      E_l = two (conv3 32->32, relu)      level 0
   s1 = E1(pool(s0)), s2 = E2(pool(s1)), z = E3(pool(s2))             levels 1-3
   d2 = D2(up(z) + s2), d1 = D1(up(d2) + s1), d0 = D0(up(d1) + s0)    D_l like E_l
   r = conv1(d0; 32->1)
-  proposal n = n0 (1 + a + r)    (then floored and renormalised by the caller)
+  proposal n = p + n0 LP(r)  (LP: low pass exp(-(|k|/k_c)^2), k_c a quarter of
+           the Nyquist frequency; then floored at 0.1 p and renormalised)
 
 conv3: 3x3x3 cross-correlation with periodic wrap (the cell is periodic) and a
 bias; conv1: 1x1x1 with bias; pool: mean over 2x2x2 blocks; up: nearest
 (each coarse value copied to its 8 fine points).  Loss: mean over the grid of
-(r - r*)^2 with r* = n_conv/n0 - 1 - a.  Parameters: 2*32+32 + 14*(27*32*32+32)
+(r - r*)^2 with r* = n_conv/n0 - 1 - b: the network learns the converged
+density's change from the previous step, guided by the superposition's change
+(the low pass keeps the short-wavelength part of its error out of the guess,
+where it slows the SCF down).  Parameters: 2*32+32 + 14*(27*32*32+32)
 + 32+1 = 387,649.
 
 Pins (tests/test_oracle_unet.py): conv3 against a brute-force loop sum on
@@ -123,9 +130,9 @@ def loss_and_grads(P, x, r_target):
 
 
 def inputs(n_guess, n_prev, n0):
-    """Network input from the one-center guess and the previous converged density."""
+    """Network input from the guide field G and the previous converged density."""
     return torch.stack([torch.as_tensor(n_guess) / n0 - 1.0, torch.as_tensor(n_prev) / n0 - 1.0])
 
 
-def target(n_conv, n_guess, n0):
-    return torch.as_tensor(n_conv) / n0 - 1.0 - (torch.as_tensor(n_guess) / n0 - 1.0)
+def target(n_conv, n_prev, n0):
+    return torch.as_tensor(n_conv) / n0 - 1.0 - (torch.as_tensor(n_prev) / n0 - 1.0)

@@ -99,6 +99,8 @@ def load(path: str = LIB_PATH):
     L.arche_debug_get.restype = st
     L.arche_debug_one_center.argtypes = [vp, _dp, _dp, _ip]
     L.arche_debug_one_center.restype = st
+    L.arche_debug_one_center2.argtypes = [vp, _dp, _dp, _ip, _dp]
+    L.arche_debug_one_center2.restype = st
     L.arche_profile_enable.argtypes = [vp, ctypes.c_int32]
     L.arche_profile_enable.restype = st
     L.arche_profile_reset.argtypes = [vp]
@@ -309,6 +311,15 @@ class Context:
         fb = ctypes.c_int32(0)
         self._check(self._L.arche_debug_one_center(self._h, _ptr(pos), _ptr(out), ctypes.byref(fb)))
         return out, bool(fb.value)
+
+    def one_center_raw(self, pos):
+        """(plain guess, used_fallback, guide G of the learned proposal) at pos."""
+        pos = _f64(pos, (self.n_atoms, 3))
+        out = np.empty(self.grid)
+        raw = np.empty(self.grid)
+        fb = ctypes.c_int32(0)
+        self._check(self._L.arche_debug_one_center2(self._h, _ptr(pos), _ptr(out), ctypes.byref(fb), _ptr(raw)))
+        return out, bool(fb.value), raw
 
     def profile(self, on=True, kinds=None):
         """Per-kernel event timing; kinds: names from PROF_NAMES (default all)."""

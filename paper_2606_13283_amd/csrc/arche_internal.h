@@ -190,8 +190,12 @@ hipError_t scf_vw_laplacian(arche_ctx* c, const double* n, double* lap);  // lap
 hipError_t scf_energies(arche_ctx* c, double* out16);  // see scf.hip for the order
 hipError_t scf_initial_uniform(arche_ctx* c);
 hipError_t scf_initial_one_center(arche_ctx* c, int* used_fallback);  // ionic.hip
-hipError_t scf_one_center_density(arche_ctx* c, int* used_fallback);  // n_i only (ionic.hip)
+// n_i only; raw: unfloored copy; delta: the superposition's change since the
+// previous step (ionic.hip)
+hipError_t scf_one_center_density(arche_ctx* c, int* used_fallback, double* raw, double* delta);
 hipError_t scf_floor_renorm(arche_ctx* c, double* n, bool* ok);       // ionic.hip
+hipError_t scf_add_scalar(arche_ctx* c, double* x, double v);         // x += v (ionic.hip)
+hipError_t scf_learned_proposal(arche_ctx* c);  // rtmp: network output r -> proposal (ionic.hip)
 hipError_t scf_prepare_input(arche_ctx* c);  // n^_i, V_H, lap sqrt(n_i) from n_i
 int scf_coop_blocks(int64_t ng);
 // the iteration's launch arguments (fills c->active, c->steps, c->fused)

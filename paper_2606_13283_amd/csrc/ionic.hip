@@ -306,10 +306,8 @@ k_pressure_ie(const cplx* nhat, const cplx* Sp, const cplx* Sm, SpeciesInfo sp, 
 }
 
 // Shells whose sum |S_Z|^2 is below SHELL_CUT x (shell size) x sum_j Z_j^2 get no
-// one-center profile: near a perfect lattice S_Z is tiny off the lattice's own
-// shells and n^/S_Z there is the nonlinear response (random positions give
-// sum |S_Z|^2 ~ (shell size) x sum Z_j^2).
-constexpr double SHELL_CUT = 1e-4;
+// one-center profile (the fit there is ill-conditioned).
+constexpr double SHELL_CUT = 1e-12;
 
 // one-center profile per shell: g = sum Re(n^ conj SZ) / sum |SZ|^2 over the full box
 __global__ void __launch_bounds__(ARCHE_BLOCK)
@@ -360,6 +358,12 @@ __global__ void __launch_bounds__(ARCHE_BLOCK) k_floor(double* n, int64_t ng, do
   if (threadIdx.x == 0) part[blockIdx.x] = raw;
   fl = block_sum(fl, sh);
   if (threadIdx.x == 0) part[gridDim.x + blockIdx.x] = fl;
+}
+
+// b <- a - b on a half spectrum
+__global__ void __launch_bounds__(ARCHE_BLOCK) k_spec_sub(const cplx* a, cplx* b, int64_t nh) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nh; i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = csub(a[i], b[i]);
 }
 
 __global__ void __launch_bounds__(ARCHE_BLOCK) k_fill_ni(double* n, int64_t ng, double v) {
@@ -507,11 +511,12 @@ hipError_t ionic_shells(arche_ctx* c) {
 
 // Floor n at GUESS_FLOOR n_0 and rescale it to N_e electrons; *ok = false (n
 // left floored, not rescaled) when the floor added more than MAX_FLOOR_CHARGE
-// of the charge (the guess is then too poor to use) or the result is not
-// finite.  A guess rings slightly negative between the ions; a floor near zero
-// would make sqrt(n), and the von Weizsaecker potential, nearly singular there.
+// of the charge or the result is not finite.  A guess that rings negative over
+// a region is rejected: floored plateaus make the von Weizsaecker potential
+// nearly singular and the SCF diverges; the few points a rounding-level ring
+// touches are floored at 1e-3 n_0 rather than near zero for the same reason.
 constexpr double GUESS_FLOOR = 1e-3;
-constexpr double MAX_FLOOR_CHARGE = 1e-2;
+constexpr double MAX_FLOOR_CHARGE = 1e-6;
 hipError_t scf_floor_renorm(arche_ctx* c, double* n, bool* ok) {
   const GridInfo& g = c->g;
   const double n0 = c->Ne / g.vol;
@@ -533,7 +538,7 @@ hipError_t scf_floor_renorm(arche_ctx* c, double* n, bool* ok) {
 // n_i = the one-center guess (Sec. 2.5.1) from the previous converged step
 // (g per shell, n^_i = g (SZ+ + SZ-)/2 at the new positions, C2R), floored and
 // rescaled; uniform when scf_floor_renorm rejects it.  No derived fields.
-hipError_t scf_one_center_density(arche_ctx* c, int* used_fallback) {
+hipError_t scf_one_center_density(arche_ctx* c, int* used_fallback, double* raw, double* delta) {
   const GridInfo& g = c->g;
   *used_fallback = 0;
   hipLaunchKernelGGL(k_shell_profile, dim3((c->nshell + ARCHE_BLOCK - 1) / ARCHE_BLOCK), dim3(ARCHE_BLOCK), 0,
@@ -543,7 +548,17 @@ hipError_t scf_one_center_density(arche_ctx* c, int* used_fallback) {
   hipLaunchKernelGGL(k_one_center_hat, dim3(grid_for(g.nh)), dim3(ARCHE_BLOCK), 0, c->stream, c->shell_g,
                      c->shell_of, c->SZp, c->SZm, g, c->ctmp);
   HIP_TRY(hipGetLastError());
+  if (delta) {
+    // the superposition's change: g^ (SZ_new - SZ_prev), into delta (via ctmp2)
+    hipLaunchKernelGGL(k_one_center_hat, dim3(grid_for(g.nh)), dim3(ARCHE_BLOCK), 0, c->stream, c->shell_g,
+                       c->shell_of, c->prev_SZp, c->prev_SZm, g, c->ctmp2);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_spec_sub, dim3(grid_for(g.nh)), dim3(ARCHE_BLOCK), 0, c->stream, c->ctmp, c->ctmp2, g.nh);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(fft_c2r(&c->plan, c->ctmp2, delta, 1.0 / g.vol, c->stream));
+  }
   HIP_TRY(fft_c2r(&c->plan, c->ctmp, c->n_i, 1.0 / g.vol, c->stream));
+  if (raw) HIP_TRY(hipMemcpyAsync(raw, c->n_i, g.ng * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   bool ok = false;
   HIP_TRY(scf_floor_renorm(c, c->n_i, &ok));
   if (!ok) {
@@ -554,7 +569,53 @@ hipError_t scf_one_center_density(arche_ctx* c, int* used_fallback) {
   return hipSuccess;
 }
 
+// s^ <- s^ exp(-(|k|/kc)^2) on the half spectrum
+__global__ void __launch_bounds__(ARCHE_BLOCK) k_spec_gauss(cplx* s, GridInfo g, double kc) {
+  for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < g.nh; m += (int64_t)gridDim.x * blockDim.x) {
+    const int iz = (int)(m % g.Nh);
+    const int64_t rr = m / g.Nh;
+    const int iy = (int)(rr % g.N[1]), ix = (int)(rr / g.N[1]);
+    const double kx = (double)(ix <= g.N[0] / 2 ? ix : ix - g.N[0]) / g.L[0];
+    const double ky = (double)(iy <= g.N[1] / 2 ? iy : iy - g.N[1]) / g.L[1];
+    const double kz = (double)iz / g.L[2];
+    s[m] = cscale(s[m], exp(-(kx * kx + ky * ky + kz * kz) / (kc * kc)));
+  }
+}
+// n = max(p + n0 r, 0.1 p)
+__global__ void __launch_bounds__(ARCHE_BLOCK)
+k_learned_combine(const double* p, const double* r, double n0, double* n, int64_t ng) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ng; i += (int64_t)gridDim.x * blockDim.x) {
+    const double rp = r[i], pp = p[i];
+    n[i] = rp == rp ? fmax(pp + n0 * rp, 0.1 * pp) : rp;
+  }
+}
+
+__global__ void __launch_bounds__(ARCHE_BLOCK) k_add_scalar(double* x, int64_t n, double v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) x[i] += v;
+}
+hipError_t scf_add_scalar(arche_ctx* c, double* x, double v) {
+  hipLaunchKernelGGL(k_add_scalar, dim3(grid_for(c->g.ng)), dim3(ARCHE_BLOCK), 0, c->stream, x, c->g.ng, v);
+  return hipGetLastError();
+}
+
+// The learned proposal from the network's output r (in rtmp): r is low-passed
+// with exp(-(|k|/kc)^2), kc a quarter of the smallest Nyquist frequency (the
+// SCF converges slowly from guesses with short-wavelength error, which the
+// network's output carries), then n = max(p + n0 r, 0.1 p) -> rtmp.
+hipError_t scf_learned_proposal(arche_ctx* c) {
+  const GridInfo& g = c->g;
+  double kc = 1e300;
+  for (int a = 0; a < 3; ++a) kc = std::min(kc, 0.25 * 0.5 * g.N[a] / g.L[a]);
+  HIP_TRY(fft_r2c(&c->plan, c->rtmp, c->ctmp, 1.0, g.dv, c->stream));
+  hipLaunchKernelGGL(k_spec_gauss, dim3(grid_for(g.nh)), dim3(ARCHE_BLOCK), 0, c->stream, c->ctmp, g, kc);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(fft_c2r(&c->plan, c->ctmp, c->lap_a, 1.0 / g.vol, c->stream));
+  hipLaunchKernelGGL(k_learned_combine, dim3(grid_for(g.ng)), dim3(ARCHE_BLOCK), 0, c->stream, c->n_a, c->lap_a,
+                     c->Ne / g.vol, c->rtmp, g.ng);
+  return hipGetLastError();
+}
+
 hipError_t scf_initial_one_center(arche_ctx* c, int* used_fallback) {
-  HIP_TRY(scf_one_center_density(c, used_fallback));
+  HIP_TRY(scf_one_center_density(c, used_fallback, nullptr, nullptr));
   return scf_prepare_input(c);
 }

@@ -277,10 +277,12 @@ k_in_bwd(const float* __restrict__ xin, const bf16* __restrict__ h, const bf16* 
   }
 }
 
-// out: r = W_out h + b_out (FP32); with a target, the loss terms and dr -> dh,
-// partial sums of the loss and of the out.w/out.b grads: part [nblk][34]
+// out: r = W_out h + b_out (FP32); with a target (r* = conv/n0 - 1 - b), the
+// loss terms and dr -> dh, partial sums of the loss and of the out.w/out.b
+// grads: part [nblk][34]
 __global__ void __launch_bounds__(256)
 k_out(const bf16* __restrict__ h, const float* __restrict__ prm, const double* __restrict__ guess,
+      const double* __restrict__ prev,
       const double* __restrict__ conv, double n0, double* __restrict__ r_out, bf16* __restrict__ dh,
       float* __restrict__ part, int64_t P) {
   __shared__ float sh[34][8];
@@ -303,8 +305,8 @@ k_out(const bf16* __restrict__ h, const float* __restrict__ prm, const double* _
     for (int c = 0; c < NC; ++c) r += w[c] * hv[c];
     if (r_out) r_out[p] = r;
     if (conv) {
-      const double a = guess[p] / n0 - 1.0;
-      const double tgt = conv[p] / n0 - 1.0 - a;
+      const double b = prev[p] / n0 - 1.0;
+      const double tgt = conv[p] / n0 - 1.0 - b;
       const float diff = (float)((double)r - tgt);
       const float dr = 2.0f * diff / (float)P;
       acc[33] += diff * diff;
@@ -439,14 +441,14 @@ k_adam(float* __restrict__ prm, const float* __restrict__ grad, float* __restric
   }
 }
 
-// proposal n = n0 (1 + a + r) = g + n0 r (a = g/n0 - 1), kept at or above
-// PROPOSAL_FLOOR g: the network corrects the guess, it does not empty a region
+// proposal n = n0 (1 + b + r) = p + n0 r: the previous converged density p
+// moved by the learned change, kept at or above PROPOSAL_FLOOR p
 constexpr double PROPOSAL_FLOOR = 0.1;
 __global__ void __launch_bounds__(256)
-k_propose(const double* __restrict__ guess, const double* __restrict__ r, double n0, double* __restrict__ n, int64_t P) {
+k_propose(const double* __restrict__ prev, const double* __restrict__ r, double n0, double* __restrict__ n, int64_t P) {
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
-    const double g = guess[p], rp = r[p];
-    n[p] = rp == rp ? fmax(g + n0 * rp, PROPOSAL_FLOOR * g) : rp;  // a NaN stays visible
+    const double rp = r[p], pp = prev[p];
+    n[p] = rp == rp ? fmax(pp + n0 * rp, PROPOSAL_FLOOR * pp) : rp;  // a NaN stays visible
   }
 }
 
@@ -675,7 +677,8 @@ arche_status arche_net_forward(arche_net* net, const double* guess, const double
   if (s != ARCHE_OK) return s;
   const Geo& g = net->g[0];
   hipLaunchKernelGGL(k_out, dim3(RED_BLOCKS), dim3(256), 0, net->stream, (const bf16*)net->dout[0],
-                     (const float*)net->prm, (const double*)nullptr, (const double*)nullptr, n0,
+                     (const float*)net->prm, (const double*)nullptr, (const double*)nullptr,
+                     (const double*)nullptr, n0,
                      r_out ? r_out : net->r, (bf16*)nullptr, net->part, g.P);
   NK(hipGetLastError());
   return ARCHE_OK;
@@ -685,7 +688,7 @@ arche_status arche_net_propose(arche_net* net, const double* guess, const double
   if (!n_out) return nerr(net, ARCHE_EINVAL, "bad argument");
   arche_status s = arche_net_forward(net, guess, prev, n0, net ? net->r : nullptr);
   if (s != ARCHE_OK) return s;
-  hipLaunchKernelGGL(k_propose, dim3(grid1(net->g[0].P)), dim3(256), 0, net->stream, guess, (const double*)net->r, n0,
+  hipLaunchKernelGGL(k_propose, dim3(grid1(net->g[0].P)), dim3(256), 0, net->stream, prev, (const double*)net->r, n0,
                      n_out, net->g[0].P);
   NK(hipGetLastError());
   return ARCHE_OK;
@@ -700,7 +703,7 @@ arche_status arche_net_loss_grad(arche_net* net, const double* guess, const doub
   // output layer, loss and dL/d dout0
   float* pout = net->part + (size_t)WG_BLOCKS_MAX * (WT + NC);
   hipLaunchKernelGGL(k_out, dim3(RED_BLOCKS), dim3(256), 0, net->stream, (const bf16*)net->dout[0],
-                     (const float*)net->prm, guess, conv, n0, net->r, net->gA[0], pout, g[0].P);
+                     (const float*)net->prm, guess, prev, conv, n0, net->r, net->gA[0], pout, g[0].P);
   NK(hipGetLastError());
   // out.w grads [0..31], out.b [32], loss sum [33]
   float* small = pout + (size_t)RED_BLOCKS * 34;

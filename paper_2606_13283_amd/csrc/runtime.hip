@@ -237,19 +237,23 @@ arche_status begin_solve(arche_ctx* c, const double* pos_host, int init, int* fa
   CK(ionic_structure(c));
   *fallback = 0;
   if (init == ARCHE_INIT_LEARNED && c->have_prev && c->init_net) {
-    // one-center guess -> n_i; proposal from [n_i, previous converged n_a] -> rtmp
-    CK(scf_one_center_density(c, fallback));
+    // plain guess -> n_i (one-center, or uniform when it rings negative); the
+    // network's input G = n0 + (superposition change since the previous step)
+    // in lap_a (free before the SCF); proposal from [G, previous converged n_a]
+    // -> rtmp, floored and renormalised
+    int plain_fb = 0;
+    CK(scf_one_center_density(c, &plain_fb, nullptr, c->lap_a));
+    CK(scf_add_scalar(c, c->lap_a, c->Ne / c->g.vol));
+    CK(hipStreamSynchronize(c->stream));
+    arche_status s = arche_net_forward(c->init_net, c->lap_a, c->n_a, c->Ne / c->g.vol, c->rtmp);
+    if (s != ARCHE_OK) return set_err(c, s, std::string("learned guess: ") + arche_net_last_error(c->init_net));
+    s = arche_net_sync(c->init_net);
+    if (s != ARCHE_OK) return set_err(c, s, std::string("learned guess: ") + arche_net_last_error(c->init_net));
+    CK(scf_learned_proposal(c));
     bool ok = false;
-    if (!*fallback) {
-      CK(hipStreamSynchronize(c->stream));
-      arche_status s = arche_net_propose(c->init_net, c->n_i, c->n_a, c->Ne / c->g.vol, c->rtmp);
-      if (s != ARCHE_OK) return set_err(c, s, std::string("learned guess: ") + arche_net_last_error(c->init_net));
-      s = arche_net_sync(c->init_net);
-      if (s != ARCHE_OK) return set_err(c, s, std::string("learned guess: ") + arche_net_last_error(c->init_net));
-      CK(scf_floor_renorm(c, c->rtmp, &ok));
-      if (ok) CK(hipMemcpyAsync(c->n_i, c->rtmp, c->g.ng * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-    }
-    if (!ok) *fallback = 1;
+    CK(scf_floor_renorm(c, c->rtmp, &ok));
+    if (ok) CK(hipMemcpyAsync(c->n_i, c->rtmp, c->g.ng * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    *fallback = ok ? 0 : 1;
     CK(scf_prepare_input(c));
   } else if ((init == ARCHE_INIT_ONE_CENTER || init == ARCHE_INIT_LEARNED) && c->have_prev) {
     CK(scf_initial_one_center(c, fallback));
@@ -581,14 +585,22 @@ arche_status arche_debug_get(arche_ctx* c, int32_t which, double* dst_host) {
 }
 
 arche_status arche_debug_one_center(arche_ctx* c, const double* pos_host, double* n_init_host, int32_t* used_fallback) {
+  return arche_debug_one_center2(c, pos_host, n_init_host, used_fallback, nullptr);
+}
+
+arche_status arche_debug_one_center2(arche_ctx* c, const double* pos_host, double* n_init_host, int32_t* used_fallback,
+                                     double* raw_host) {
   if (!c || !pos_host || !n_init_host) return set_err(c, ARCHE_EINVAL, "NULL argument");
   if (!c->have_prev) return set_err(c, ARCHE_ESTATE, "no previous converged step");
   c->h_pos.assign(pos_host, pos_host + 3 * c->n_atoms);
   CK(hipMemcpyAsync(c->pos, pos_host, 3 * c->n_atoms * sizeof(double), hipMemcpyHostToDevice, c->stream));
   CK(ionic_structure(c));
   int fb = 0;
-  CK(scf_initial_one_center(c, &fb));
+  CK(scf_one_center_density(c, &fb, nullptr, c->lap_a));
+  CK(scf_add_scalar(c, c->lap_a, c->Ne / c->g.vol));
+  CK(scf_prepare_input(c));
   if (used_fallback) *used_fallback = fb;
+  if (raw_host) CK(hipMemcpyAsync(raw_host, c->lap_a, c->g.ng * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   CK(hipMemcpyAsync(n_init_host, c->n_i, c->g.ng * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   CK(hipStreamSynchronize(c->stream));
   c->solved = false;

@@ -1,9 +1,10 @@
 """Training and evaluation driver of the learned initial density (arche_net.h).
 
 Samples come from the method itself: an MD trajectory with the plain
-(one-center) guess, where each step records, at the new positions, the
-one-center guess g, the previous converged density p and the converged density
-n.  The network learns r = n/n0 - 1 - (g/n0 - 1) from [g, p].  Every numerical
+(one-center) guess, where each step records, at the new positions, the guide
+G = n0 + the one-center superposition's change since the previous step, the
+previous converged density p and the converged density n.  The network learns
+r = n/n0 - 1 - (p/n0 - 1), the converged density's change, from [G, p].  Every numerical
 step runs in the library's kernels; this module only sequences the calls and
 keeps the samples in device memory (torch tensors).
 """
@@ -73,9 +74,9 @@ class Trajectory:
         sample = None
         if record:
             p = self.ctx.density()
-            g, fb = self.ctx.one_center_guess(r_next)
+            _, _, g = self.ctx.one_center_raw(r_next)
         res = self.ctx.solve(r_next)
-        if record and not fb:
+        if record:
             sample = (_dev(g), _dev(p), _dev(self.ctx.density()))
         self.r_prev, self.r = self.r, r_next
         self.F = self.ctx.forces()
@@ -124,18 +125,24 @@ def train(net, samples, n0s, epochs, lr=1e-3, seed=0, lr_end=1e-4):
 
 
 def compare(w, net, steps):
-    """Plain (one-center) and learned guesses solved at the same positions: the
-    plain trajectory drives the positions, the learned context follows it.
-    Returns per-step SCF iterations and free energies of both."""
+    """The plain guess (one-center, uniform where it rings negative), the
+    previous converged density alone (what an untrained network proposes) and
+    the learned proposal, solved at the same positions: the plain trajectory
+    drives the positions, the others follow it.  Per-step SCF iterations and
+    free energies."""
     plain = Trajectory(w)
+    prev = Trajectory(w, init=arche.INIT_KEEP)
     learned = Trajectory(w, init=arche.INIT_LEARNED, net=net)
     rows = []
     for _ in range(steps):
         r_next = plain.next_positions()
         a, _ = plain.step(r_next)
+        prev.ctx.set_density(prev.ctx.density())
+        c, _ = prev.step(r_next)
         b, _ = learned.step(r_next)
-        rows.append({"plain_iters": a["scf_iters"], "learned_iters": b["scf_iters"], "F_plain": a["F"],
-                     "F_learned": b["F"], "fallback": b["used_fallback"]})
-    plain.close()
-    learned.close()
+        rows.append({"plain_iters": a["scf_iters"], "plain_fallback": a["used_fallback"],
+                     "prev_iters": c["scf_iters"], "learned_iters": b["scf_iters"], "F_plain": a["F"],
+                     "F_prev": c["F"], "F_learned": b["F"], "fallback": b["used_fallback"]})
+    for t in (plain, prev, learned):
+        t.close()
     return rows

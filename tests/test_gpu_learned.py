@@ -58,8 +58,11 @@ def test_learned_guess_saves_iterations(trained):
         assert r["fallback"] == 0
         assert abs(r["F_learned"] - r["F_plain"]) <= 1e-9 * abs(r["F_plain"])
     plain = np.mean([r["plain_iters"] for r in rows])
+    prev = np.mean([r["prev_iters"] for r in rows])
     lrn = np.mean([r["learned_iters"] for r in rows])
-    say("mean SCF iterations: one-center %.1f, learned %.1f" % (plain, lrn))
+    say("mean SCF iterations: plain guess %.1f, previous density alone %.1f, learned %.1f" % (plain, prev, lrn))
+    for r in rows:
+        assert abs(r["F_prev"] - r["F_plain"]) <= 1e-9 * abs(r["F_plain"])
     assert lrn < plain
 
 

@@ -168,7 +168,7 @@ def test_backward_conv_layers(run):
 def test_end_to_end_against_oracle(run):
     net, P, (g, p, c, n0), loss = run
     x = U.inputs(g, p, n0)
-    t = U.target(c, g, n0)
+    t = U.target(c, p, n0)
     L_ref, G_ref = U.loss_and_grads(P, x, t)
     r_ref = U.forward(P, x).numpy()
     r = torch.empty(GRID, dtype=torch.float64, device="cuda")
