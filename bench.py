@@ -10,9 +10,13 @@ positions and Maxwell-Boltzmann velocities.
 A step is one MD step: structure factor and ionic field, one-center guess,
 the SCF to convergence, free energy and pressure, forces, Verlet update.
 Prints one JSON line.  The value is SCF iterations per second over the timed
-steps; the wall time per MD step is ms_per_step.
+steps; the wall time per MD step is ms_per_step.  Two more comparisons ride
+along (untimed for `value`): "batch" (64 independent 108-atom snapshots solved
+one after another vs in one batch) and "learned_init" (plain guess vs previous
+density vs the learned proposal on 256-atom MD at 64^3).
 
-  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--batch N] [--learned K]
+                  [--no-cpu-baseline] [--copy-probe MIB]
 """
 from __future__ import annotations
 
@@ -33,9 +37,10 @@ METRIC = "SCF iters/s + wall s per MD step (plain vs learned-init/batched), 1024
 def kernel_bytes(name, ng, nh, newton_per_launch):
     """Algorithmic HBM bytes of one launch of each timed kernel class."""
     if name == "scf_active":
-        # potential assembly: read n_i, V^ie, V_H, lap sqrt(n_i), write V_i (40 B/pt);
-        # each Newton pass reads V_i (8 B/pt); final pass reads V_i, n_i, writes n_a (24 B/pt)
-        return ng * (40.0 + 8.0 * newton_per_launch + 24.0)
+        # potential assembly: read n_i, V^ie, V_H, lap sqrt(n_i), write V_i (40 B/pt); the
+        # Newton passes read nothing (V_i stays in registers); the last phase reads n_i and
+        # writes n_a (16 B/pt)
+        return ng * 56.0
     if name == "fft_z":
         return ng * 8.0 + nh * 16.0  # real field in/out + half spectrum out/in
     if name == "fft_strided":
@@ -139,6 +144,67 @@ def bench_batch(count):
             "bit_identical_to_sequential": bool(same), "schedule": info2, "tuning": info1}
 
 
+def bench_learned(steps_train, epochs, steps_eval):
+    """The learned initial density on 256 Al atoms at 64^3: training samples from
+    plain MD at 2, 4, 6, 8, 10 eV (`steps_train` steps each), `epochs` of Adam on
+    the GPU, then a held-out 5 eV trajectory of `steps_eval` MD steps solved
+    from the plain guess, from the previous converged density alone and from
+    the learned proposal at the same positions.  Wall time per MD step and SCF
+    iterations of each, the free energies agreeing to 1e-9."""
+    import numpy as np
+    import torch
+
+    from paper_2606_13283_amd import arche
+    from paper_2606_13283_amd import learned as LN
+    from paper_2606_13283_amd import workloads as W
+
+    ws = [W.fcc256_at(T, seed=100 + i) for i, T in enumerate((2.0, 4.0, 6.0, 8.0, 10.0))]
+    t0 = time.perf_counter()
+    samples = LN.generate(ws, steps=steps_train)
+    t_gen = time.perf_counter() - t0
+    net = arche.Net((64, 64, 64))
+    net.set_params(LN.init_params(0))
+    data = [s for s, _ in samples]
+    n0s = [LN.n0_of(ws[0])] * len(data)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = LN.train(net, data, n0s, epochs=epochs, lr=1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    n_train_steps = epochs * len(data)
+    w = W.fcc256_at(5.0, seed=300)
+    trs = {"plain": LN.Trajectory(w), "previous_density": LN.Trajectory(w, init=arche.INIT_KEEP),
+           "learned": LN.Trajectory(w, init=arche.INIT_LEARNED, net=net)}
+    wall = {k: 0.0 for k in trs}
+    iters = {k: [] for k in trs}
+    Fs = {k: [] for k in trs}
+    for _ in range(steps_eval):
+        r_next = trs["plain"].next_positions()
+        for k, tr in trs.items():
+            if k == "previous_density":
+                tr.ctx.set_density(tr.ctx.density())
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res, _ = tr.step(r_next)
+            torch.cuda.synchronize()
+            wall[k] += time.perf_counter() - t0
+            iters[k].append(res["scf_iters"])
+            Fs[k].append(res["F"])
+    for tr in trs.values():
+        tr.close()
+    net.close()
+    same = all(abs(a - b) <= 1e-9 * abs(a) for k in ("previous_density", "learned") for a, b in zip(Fs["plain"], Fs[k]))
+    print("[bench] learned: iterations plain %.1f, previous density %.1f, learned %.1f" % tuple(
+        float(np.mean(iters[k])) for k in ("plain", "previous_density", "learned")), file=sys.stderr, flush=True)
+    return {"workload": "fcc256_64^3 MD at 5 eV (held out), trained on 2-10 eV", "samples": len(data),
+            "epochs": epochs, "sample_generation_s": t_gen, "training_s": t_train,
+            "training_steps_per_s": n_train_steps / t_train, "loss_first_last_epoch": [hist[0], hist[-1]],
+            "md_steps": steps_eval,
+            "wall_s_per_md_step": {k: wall[k] / steps_eval for k in wall},
+            "scf_iters_per_md_step": {k: float(np.mean(iters[k])) for k in iters},
+            "scf_iters_each_step": iters, "free_energy_agrees_1e-9": bool(same)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,6 +214,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--batch", type=int, default=64, help="snapshots of the batched-solve comparison (0: skip)")
+    ap.add_argument("--learned", type=int, default=8, help="MD steps of the learned-init comparison (0: skip)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device 5 times (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -269,6 +336,8 @@ def main():
     }
     if args.batch > 0:
         out["batch"] = bench_batch(args.batch)
+    if args.learned > 0:
+        out["learned_init"] = bench_learned(16, 12, args.learned)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out))
