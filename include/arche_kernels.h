@@ -33,6 +33,13 @@ arche_status arche_k_fft_c2r(const int32_t grid[3], const double *d_in, double *
 arche_status arche_k_fermi_dirac(int64_t n, const double *d_x, double *d_im12, double *d_ip12, double *d_ip32,
                                  void *stream);
 
+/* I_{1/2}(x) and its first three derivatives in x at n points d_x, as the SCF
+ * kernel evaluates them: d_d1 = I_{-1/2}/2 (dI_j/dx = j I_{j-1}), which drives
+ * the Newton search of mu (eq. newtonmu); d_d2 and d_d3 build the cubic model of
+ * N(mu) that starts that search.  Any output may be NULL.  Blocks until done. */
+arche_status arche_k_fermi_dirac_derivs(int64_t n, const double *d_x, double *d_d0, double *d_d1, double *d_d2,
+                                        double *d_d3, void *stream);
+
 /* Copies of internal fields of a context after a solve (host destination). */
 enum {
   ARCHE_DBG_VIE = 0,    /* V^ie(r) [ng] (Sec. 2.4) */

@@ -160,6 +160,8 @@ def load(path: str = LIB_PATH):
     L.arche_k_fft_c2r.restype = st
     L.arche_k_fermi_dirac.argtypes = [ctypes.c_int64, vp, vp, vp, vp, vp]
     L.arche_k_fermi_dirac.restype = st
+    L.arche_k_fermi_dirac_derivs.argtypes = [ctypes.c_int64, vp, vp, vp, vp, vp, vp]
+    L.arche_k_fermi_dirac_derivs.restype = st
     _lib = L
     return L
 
@@ -554,6 +556,20 @@ def fermi_dirac(x):
     if s != OK:
         raise ArcheError(s, "arche_k_fermi_dirac")
     return a, b, c
+
+
+def fermi_dirac_derivs(x):
+    """I_{1/2} and its first three derivatives at a float64 cuda tensor, from the SCF kernel's table."""
+    import torch
+    L = load()
+    x = x.contiguous()
+    out = [torch.empty_like(x) for _ in range(4)]
+    s = L.arche_k_fermi_dirac_derivs(x.numel(), ctypes.c_void_p(x.data_ptr()),
+                                     *[ctypes.c_void_p(o.data_ptr()) for o in out],
+                                     ctypes.c_void_p(torch.cuda.current_stream(x.device).cuda_stream))
+    if s != OK:
+        raise ArcheError(s, "arche_k_fermi_dirac_derivs")
+    return tuple(out)
 
 
 def version():

@@ -21,6 +21,22 @@ k_fd_eval(const FdTables* fdt, int64_t n, const double* x, double* im12, double*
   }
 }
 
+// d^m I_{1/2}/dx^m, m = 0..3, as the SCF kernel evaluates them (LDS table)
+__global__ void __launch_bounds__(ARCHE_BLOCK)
+k_fd_derivs(const FdTables* fdt, int64_t n, const double* x, double* d0, double* d1, double* d2, double* d3) {
+  __shared__ FdLds fdl;
+  fd_lds_load(&fdl, fdt);
+  __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double d[4];
+    fd_p12_derivs<3>(fdl, x[i], d);
+    if (d0) d0[i] = d[0];
+    if (d1) d1[i] = d[1];
+    if (d2) d2[i] = d[2];
+    if (d3) d3[i] = d[3];
+  }
+}
+
 std::mutex g_plan_mtx;
 std::map<std::tuple<int, int, int, int>, FftPlan*> g_plans;  // (device, Nx, Ny, Nz), kept for the process
 
@@ -87,6 +103,22 @@ arche_status arche_k_fermi_dirac(int64_t n, const double* d_x, double* d_im12, d
   int64_t b = (n + ARCHE_BLOCK - 1) / ARCHE_BLOCK;
   if (b > 4096) b = 4096;
   hipLaunchKernelGGL(k_fd_eval, dim3((unsigned)b), dim3(ARCHE_BLOCK), 0, s, t, n, d_x, d_im12, d_ip12, d_ip32);
+  if (hipGetLastError() != hipSuccess) return ARCHE_EHIP;
+  return hipStreamSynchronize(s) == hipSuccess ? ARCHE_OK : ARCHE_EHIP;
+}
+
+arche_status arche_k_fermi_dirac_derivs(int64_t n, const double* d_x, double* d_d0, double* d_d1, double* d_d2,
+                                        double* d_d3, void* stream) {
+  if (n < 0 || (n > 0 && !d_x)) return ARCHE_EINVAL;
+  if (n == 0) return ARCHE_OK;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return ARCHE_EHIP;
+  const FdTables* t = fd_tables_device(dev);
+  if (!t) return ARCHE_ENOMEM;
+  hipStream_t s = (hipStream_t)stream;
+  int64_t b = (n + ARCHE_BLOCK - 1) / ARCHE_BLOCK;
+  if (b > 4096) b = 4096;
+  hipLaunchKernelGGL(k_fd_derivs, dim3((unsigned)b), dim3(ARCHE_BLOCK), 0, s, t, n, d_x, d_d0, d_d1, d_d2, d_d3);
   if (hipGetLastError() != hipSuccess) return ARCHE_EHIP;
   return hipStreamSynchronize(s) == hipSuccess ? ARCHE_OK : ARCHE_EHIP;
 }

@@ -12,11 +12,6 @@ namespace {
 
 constexpr double PI = 3.14159265358979323846;
 
-// ---------------------------------------------------------------------------
-__device__ inline void put_slot(double* part, int slot, unsigned nb, double v) {
-  if (threadIdx.x == 0) coherent_store(part + (size_t)slot * nb + blockIdx.x, v);  // read by grid_allreduce
-}
-
 
 // The grid is cut into chunks of SCF_CHUNK consecutive points; thread t of the
 // block that owns a chunk handles points t + ARCHE_BLOCK*q, q < PPT.  Every
@@ -31,106 +26,89 @@ constexpr double MU_SETTLED = 0.02;
 // (the quadratic model can send it to 0 in one step in low-density regions)
 constexpr double W_MAX_DROP = 0.05;
 constexpr int SCF_CHUNK = ARCHE_BLOCK * PPT;
+// the chemical potential is found once |N(mu) - N_e| <= MU_TOL N_e
+constexpr double MU_TOL = 1e-14;
+// after a Newton evaluation with |N - N_e| <= SPEC_NEWTON N_e the next pass is
+// most likely the last (quadratic convergence) and forms the active sums too
+constexpr double SPEC_NEWTON = 1e-7;
+// LDS doubles for block_reduce_n<8>
+constexpr int RED_SH = (ARCHE_BLOCK / 64) * 8;
 
-__device__ inline void put_chunk(double* part, int slot, int64_t nchunk, int64_t c, double v) {
-  if (threadIdx.x == 0) coherent_store(part + (int64_t)slot * nchunk + c, v);  // read by grid_allreduce
+// The first NV block-reduced values of acc go to slots s0.. of chunk c.
+template <int NV>
+__device__ inline void put_chunk_n(const double* acc, double* part, int s0, int64_t nchunk, int64_t c) {
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) coherent_store(part + (int64_t)(s0 + k) * nchunk + c, acc[k]);  // read by grid_allreduce
+  }
 }
 
-// Steps 1-4 of one SCF iteration for one system, run by a group of G
-// co-resident blocks (lb = this block's index in the group):
-//  1. V_i = V^ie + V_H[n_i] + v_xc(n_i) + v_vW[n_i]
-//  2. Newton search of mu with N(mu) = int c_n I_{1/2}((mu - V_i)/kT) = N_e
-//     (eq. newtonmu), safeguarded by bisection in [min V_i, max V_i] + kT eta_0
-//  3. n_a, dn = n_i - n_a, and the reductions K, ||dn||, ||n_a||, U_xc, max|dn|/n_a
-//  4. convergence test and the More switch
-// grid_allreduce hands every block of the group the same fixed-order result, so
-// all of them take the same branches.  With CACHE (at most one chunk per block)
-// V_i and v_xc(n_i) stay in registers between the phases.
-// Phase-3 work for one chunk at chemical potential mu: n_a = c_n I_{1/2}(eta_a)
-// is stored, and the six sums of the residual and of More's weight are put in
-// slots s0..s0+5 (the last one a max).
-template <bool CACHE>
-__device__ inline void active_sums(const ActiveArgs& a, int64_t c, const double* vreg, double mu, double ikT,
-                                   const FdLds& fdl, double* sh, int s0) {
+// Sums for one chunk at chemical potential mu, eta = (mu - V_i)/kT:
+//   slots 0, 1: sum I_{1/2}(eta), sum dI_{1/2}/deta (N(mu) and N'(mu) up to
+//               the factors dv c_n and dv c_n / kT)
+// and with ACTIVE, which also stores n_a = c_n I_{1/2}(eta):
+//   slots 2..7: sum dn^2, sum n_a^2, K, U_xc, sum n_a, max |dn|/n_a
+//   (dn = n_i - n_a; K is the secant of the Thomas-Fermi potential kT eta(n)
+//   between n_a and n_i, U_xc the same for v_xc)
+// With CACHE, vreg and xreg hold this thread's V_i and v_xc(n_i) from the assembly.
+template <bool CACHE, bool ACTIVE>
+__device__ inline void chunk_sums(const ActiveArgs& a, int64_t c, const double* vreg, const double* xreg, double mu,
+                                  double ikT, const FdLds& fdl, double* sh) {
   const bool more = a.mixing == ARCHE_MIX_MORE;
-  double sdd = 0.0, snn = 0.0, sK = 0.0, sU = 0.0, sNa = 0.0, smax = 0.0;
+  const double icn = 1.0 / a.cn;
+  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   for (int q = 0; q < PPT; ++q) {
     const int64_t i = c * SCF_CHUNK + threadIdx.x + (int64_t)ARCHE_BLOCK * q;
     if (i < a.ng) {
-      double im, ip;
       const double v = CACHE ? vreg[q] : a.Vi[i];
-      fd_m12_p12_lds(fdl, (mu - v) * ikT, im, ip);
-      const double na = a.cn * ip;
-      const double ni = a.n_i[i];
-      const double d = ni - na;
-      a.n_a[i] = na;
-      sdd += d * d;
-      snn += na * na;
-      if (more) {
-        // K: secant of the Thomas-Fermi potential kT eta(n) between n_a and n_i
-        const double eta_a = (mu - v) * ikT;
-        const double eta_i = fd_p12_inverse_from(fdl, ni / a.cn, eta_a, ip, im);
-        sK += a.kT * (eta_i - eta_a) * d;
+      const double eta = (mu - v) * ikT;
+      double d[ACTIVE ? 4 : 2];
+      fd_p12_derivs<ACTIVE ? 3 : 1>(fdl, eta, d);
+      acc[0] += d[0];
+      acc[1] += d[1];
+      if (ACTIVE) {
+        const double na = a.cn * d[0];
+        const double ni = a.n_i[i];
+        const double dn = ni - na;
+        a.n_a[i] = na;
+        acc[2] += dn * dn;
+        acc[3] += na * na;
+        if (more) acc[4] += a.kT * fd_p12_shift(fdl, ni * icn, eta, d) * dn;  // kT (eta_i - eta_a) dn
+        if (a.xc) {
+          double vi, va;
+          if (CACHE)
+            vi = xreg[q];
+          else
+            lda_xc(ni, vi);
+          lda_xc(na, va);
+          acc[5] += (vi - va) * dn;
+        }
+        acc[6] += na;
+        acc[7] = fmax(acc[7], fabs(dn) / na);
       }
-      sNa += na;
-      if (a.xc) {
-        double vi, va;
-        lda_xc(ni, vi);
-        lda_xc(na, va);
-        sU += (vi - va) * d;
-      }
-      smax = fmax(smax, fabs(d) / na);
     }
   }
-  const int64_t nchunk = a.nchunk;
-  double v;
-  v = block_sum(sdd, sh);
-  put_chunk(a.part, s0, nchunk, c, v);
-  v = block_sum(snn, sh);
-  put_chunk(a.part, s0 + 1, nchunk, c, v);
-  v = block_sum(sK, sh);
-  put_chunk(a.part, s0 + 2, nchunk, c, v);
-  v = block_sum(sU, sh);
-  put_chunk(a.part, s0 + 3, nchunk, c, v);
-  v = block_sum(sNa, sh);
-  put_chunk(a.part, s0 + 4, nchunk, c, v);
-  v = block_max(smax, sh);
-  put_chunk(a.part, s0 + 5, nchunk, c, v);
-}
-
-// The chunk's sums of I_{1/2} and I_{-1/2} at mu into slots s0, s0+1.
-template <bool CACHE>
-__device__ inline void newton_sums(const ActiveArgs& a, int64_t c, const double* vreg, double mu, double ikT,
-                                   const FdLds& fdl, double* sh, int s0) {
-  double s12 = 0.0, sm12 = 0.0;
-  for (int q = 0; q < PPT; ++q) {
-    const int64_t i = c * SCF_CHUNK + threadIdx.x + (int64_t)ARCHE_BLOCK * q;
-    if (i < a.ng) {
-      double im, ip;
-      const double v = CACHE ? vreg[q] : a.Vi[i];
-      fd_m12_p12_lds(fdl, (mu - v) * ikT, im, ip);
-      s12 += ip;
-      sm12 += im;
-    }
-  }
-  double b = block_sum(s12, sh);
-  put_chunk(a.part, s0, a.nchunk, c, b);
-  b = block_sum(sm12, sh);
-  put_chunk(a.part, s0 + 1, a.nchunk, c, b);
+  block_reduce_n<ACTIVE ? 8 : 2>(acc, ACTIVE ? 0x80u : 0u, sh);
+  put_chunk_n<ACTIVE ? 8 : 2>(acc, a.part, 0, a.nchunk, c);
 }
 
 // Steps 1-4 of one SCF iteration for one system, run by a group of G
 // co-resident blocks (lb = this block's index in the group).
 //   1. V_i = V^ie + V_H + v_xc(n_i) + v_vW[n_i] with its sum, max and min, and
-//      the first Newton evaluation N(mu), N'(mu) at the previous iteration's mu
-//   2. Newton search of mu (safeguarded by bisection): N(mu) = N_e
+//      at the previous iteration's mu the sums of I_{1/2} and of its first
+//      three derivatives: N(mu) and its cubic Taylor model about that mu
+//   2. Newton search of mu (safeguarded by bisection) for N(mu) = N_e,
+//      started from the root of the cubic model: mu moves little between
+//      iterations, so the model's root is usually exact to MU_TOL and one pass
+//      confirms it
 //   3. n_a at mu with the sums of the residual and of More's weight; a Newton
-//      pass that follows a small residual |N - N_e| forms them too, so when it
+//      pass that is expected to be the last forms them too, so when it
 //      converges no separate pass is needed
 //   4. the SCF scalars (block 0)
 // grid_allreduce hands every block of the group the same fixed-order result, so
 // all of them take the same branches.  With CACHE (at most one chunk per block)
-// V_i stays in registers between the phases.
+// V_i and v_xc(n_i) stay in registers between the phases; V_i is stored only
+// by the iteration that ends the solve (the energies of Sec. 2.6 read it).
 template <bool CACHE>
 __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigned G, const FdLds& fdl, double* sh,
                                        double* r) {
@@ -138,7 +116,7 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
   unsigned* go = a.flags + G;
   unsigned epoch = (unsigned)(st->iter + 1) * 256u;  // grows by one per all-reduce; disjoint per launch
   const int64_t nchunk = a.nchunk;
-  double vreg[CACHE ? PPT : 1];
+  double vreg[CACHE ? PPT : 1], xreg[CACHE ? PPT : 1];
   const double kT = a.kT;
   const double ikT = 1.0 / kT;
   const double mu_prev = st->mu;  // NaN on the first iteration
@@ -147,68 +125,105 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
 #define FOR_CHUNKS(c)                                           \
   for (int64_t c = lb; c < nchunk; c += (CACHE ? nchunk : G))
 
-  // 1. potential assembly (+ N, N' at the previous mu)
+  // 1. potential assembly (+ the Taylor sums of N at the previous mu)
   FOR_CHUNKS(c) {
-    double vmin = INFINITY, vmax = -INFINITY, vsum = 0.0;
+    double acc[7] = {0.0, -INFINITY, -INFINITY, 0.0, 0.0, 0.0, 0.0};
     for (int q = 0; q < PPT; ++q) {
       const int64_t i = c * SCF_CHUNK + threadIdx.x + (int64_t)ARCHE_BLOCK * q;
       if (i < a.ng) {
         const double n = a.n_i[i];
         double v = a.Vie[i] + a.VH[i];
+        double vxc = 0.0;
         if (a.xc) {
-          double vxc;
           lda_xc(n, vxc);
           v += vxc;
         }
         if (a.lam != 0.0) v += -0.5 * a.lam * a.lap_i[i] / sqrt(n);
-        if (CACHE) vreg[q] = v;
-        a.Vi[i] = v;
-        vmin = fmin(vmin, v);
-        vmax = fmax(vmax, v);
-        vsum += v;
+        if (CACHE) {
+          vreg[q] = v;
+          xreg[q] = vxc;
+        } else {
+          a.Vi[i] = v;
+        }
+        acc[0] += v;
+        acc[1] = fmax(acc[1], v);
+        acc[2] = fmax(acc[2], -v);
+        if (try_prev) {
+          double d[4];
+          fd_p12_derivs<3>(fdl, (mu_prev - v) * ikT, d);
+          acc[3] += d[0];
+          acc[4] += d[1];
+          acc[5] += d[2];
+          acc[6] += d[3];
+        }
       }
     }
-    double v = block_sum(vsum, sh);
-    put_chunk(a.part, 0, nchunk, c, v);
-    v = block_max(vmax, sh);
-    put_chunk(a.part, 1, nchunk, c, v);
-    v = block_max(-vmin, sh);
-    put_chunk(a.part, 2, nchunk, c, v);
-    if (try_prev) newton_sums<CACHE>(a, c, vreg, mu_prev, ikT, fdl, sh, 3);
+    block_reduce_n<7>(acc, 0x6u, sh);
+    put_chunk_n<7>(acc, a.part, 0, nchunk, c);
   }
-  grid_allreduce(a.part, nchunk, a.res, 0, try_prev ? 5 : 3, 0x6u, G, lb, a.flags, go, ++epoch, a.err, r, sh);
+  grid_allreduce(a.part, nchunk, a.res, 0, try_prev ? 7 : 3, 0x6u, G, lb, a.flags, go, ++epoch, a.err, r, sh);
   const double Vsum = r[0], Vmax = r[1], Vmin = -r[2];
-  const double pre12 = r[3], pre_m12 = r[4];
+  const double scale = a.dv * a.cn;  // N = scale * sum I_{1/2}
   double lo = Vmin + kT * a.eta0;
   double hi = Vmax + kT * a.eta0;
   double mu = mu_prev;
   const bool use_prev = try_prev && lo <= mu && mu <= hi;
   if (!use_prev) mu = Vsum / (double)a.ng + kT * a.eta0;
 
-  // 2. Newton search of mu
-  int it;
-  bool found = false, have_sums = false;
-  double N = 0.0, dN = 0.0, fprev = INFINITY;
+  // 2. the mu search; it counts the evaluations of N(mu)
+  int it = 0;
+  bool found = false, have_sums = false, spec = false;
+  double N = 0.0, dN = 0.0;
   double D[6] = {0, 0, 0, 0, 0, 0};
-  for (it = 1; it <= a.max_newton; ++it) {
-    bool spec = false;
-    if (it == 1 && use_prev) {
-      N = a.dv * a.cn * pre12;
-      dN = a.dv * a.cn * 0.5 * ikT * pre_m12;
-    } else {
-      // quadratic convergence: after |N - N_e| <= 1e-7 N_e this pass is most likely the last
-      spec = fabs(fprev) <= 1e-7 * a.Ne;
-      FOR_CHUNKS(c) {
-        newton_sums<CACHE>(a, c, vreg, mu, ikT, fdl, sh, 0);
-        if (spec) active_sums<CACHE>(a, c, vreg, mu, ikT, fdl, sh, 2);
-      }
-      grid_allreduce(a.part, nchunk, a.res, 0, spec ? 8 : 2, spec ? 0x80u : 0u, G, lb, a.flags, go, ++epoch, a.err,
-                     r, sh);
-      N = a.dv * a.cn * r[0];
-      dN = a.dv * a.cn * 0.5 * ikT * r[1];
-    }
+  if (use_prev) {
+    it = 1;
+    N = scale * r[3];
+    dN = scale * ikT * r[4];
     const double f = N - a.Ne;
-    if (fabs(f) <= 1e-14 * a.Ne) {
+    if (fabs(f) <= MU_TOL * a.Ne) {
+      found = true;
+    } else {
+      if (f > 0.0)
+        hi = mu;
+      else
+        lo = mu;
+      // root z = (mu - mu_prev)/kT of g(z) = g0 + g1 z + g2 z^2 + g3 z^3, the
+      // cubic Taylor model of (N(mu) - N_e)/scale, by Newton from z = 0
+      const double g0 = r[3] - a.Ne / scale, g1 = r[4], g2 = 0.5 * r[5], g3 = r[6] / 6.0;
+      double z = 0.0;
+      for (int k = 0; k < 8; ++k) {
+        const double gz = fma(z, fma(z, fma(z, g3, g2), g1), g0);
+        const double gp = fma(z, fma(z, 3.0 * g3, 2.0 * g2), g1);
+        const double s = gz / gp;
+        z -= s;
+        if (fabs(s) <= 1e-16 * (1.0 + fabs(z))) break;
+      }
+      double mn = mu + kT * z;
+      // the model's error is of order z^4/24 of N (the non-degenerate bound,
+      // where every derivative of I_{1/2} equals I_{1/2}); when that is within
+      // MU_TOL the pass at the root forms the active sums as well
+      spec = z * z * z * z * (1.0 / 24.0) <= 0.5 * MU_TOL;
+      if (!(lo < mn && mn < hi)) {
+        mn = mu - f / dN;
+        if (!(lo < mn && mn < hi)) mn = 0.5 * (lo + hi);
+        spec = false;
+      }
+      mu = mn;
+    }
+  }
+  while (!found && it < a.max_newton) {
+    ++it;
+    if (spec) {
+      FOR_CHUNKS(c) chunk_sums<CACHE, true>(a, c, vreg, xreg, mu, ikT, fdl, sh);
+      grid_allreduce(a.part, nchunk, a.res, 0, 8, 0x80u, G, lb, a.flags, go, ++epoch, a.err, r, sh);
+    } else {
+      FOR_CHUNKS(c) chunk_sums<CACHE, false>(a, c, vreg, xreg, mu, ikT, fdl, sh);
+      grid_allreduce(a.part, nchunk, a.res, 0, 2, 0u, G, lb, a.flags, go, ++epoch, a.err, r, sh);
+    }
+    N = scale * r[0];
+    dN = scale * ikT * r[1];
+    const double f = N - a.Ne;
+    if (fabs(f) <= MU_TOL * a.Ne) {
       found = true;
       if (spec) {
         have_sums = true;
@@ -216,7 +231,6 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
       }
       break;
     }
-    fprev = f;
     if (f > 0.0)
       hi = mu;
     else
@@ -228,22 +242,32 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
       found = true;
       break;
     }
+    spec = fabs(f) <= SPEC_NEWTON * a.Ne;
     mu = mn;
   }
-  if (it > a.max_newton) it = a.max_newton;
 
-  // 3. active density and the mixing reductions (unless the last Newton pass formed them)
+  // 3. active density and the mixing reductions (unless the last pass formed them)
   if (!have_sums) {
-    FOR_CHUNKS(c) active_sums<CACHE>(a, c, vreg, mu, ikT, fdl, sh, 0);
-    grid_allreduce(a.part, nchunk, a.res, 0, 6, 0x20u, G, lb, a.flags, go, ++epoch, a.err, r, sh);
-    for (int k = 0; k < 6; ++k) D[k] = r[k];
+    FOR_CHUNKS(c) chunk_sums<CACHE, true>(a, c, vreg, xreg, mu, ikT, fdl, sh);
+    grid_allreduce(a.part, nchunk, a.res, 0, 8, 0x80u, G, lb, a.flags, go, ++epoch, a.err, r, sh);
+    for (int k = 0; k < 6; ++k) D[k] = r[2 + k];
+  }
+  const double DD = D[0], NN = D[1], KK = D[2], UU = D[3], NA = D[4], MX = D[5];
+  const double res = sqrt(DD / NN);
+  const int t = st->iter;
+  // every block reaches the same verdict (the sums are identical in all of them)
+  const bool last = res < a.tol || !(res == res) || !found || t + 1 >= a.max_iter;
+  if (CACHE && last) {
+    FOR_CHUNKS(c) {
+      for (int q = 0; q < PPT; ++q) {
+        const int64_t i = c * SCF_CHUNK + threadIdx.x + (int64_t)ARCHE_BLOCK * q;
+        if (i < a.ng) a.Vi[i] = vreg[q];
+      }
+    }
   }
 #undef FOR_CHUNKS
-  const double DD = D[0], NN = D[1], KK = D[2], UU = D[3], NA = D[4], MX = D[5];
 
   if (lb == 0 && threadIdx.x == 0) {
-    const double res = sqrt(DD / NN);
-    const int t = st->iter;
     int more = st->more_on;
     if (a.mixing == ARCHE_MIX_MORE && !more && t >= a.warmup &&
         (MX <= a.trust || fabs(mu - mu_prev) <= MU_SETTLED * kT))
@@ -263,14 +287,14 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
     if (!found) st->mu_fail = 1;
     const bool bad = !(res == res) || !found || *a.err;
     if (bad) st->err = 1;
-    st->done = (res < a.tol) || bad || (t + 1 >= a.max_iter);
+    st->done = last || bad;
   }
 }
 
 // One system: the whole cooperative grid is the group.
 template <bool CACHE>
 __global__ void __launch_bounds__(ARCHE_BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) k_scf_active(ActiveArgs a) {
-  __shared__ double sh[ARCHE_BLOCK / 64];
+  __shared__ double sh[RED_SH];
   __shared__ double r[8];
   __shared__ FdLds fdl;
   if (a.st->done) return;
@@ -283,7 +307,7 @@ __global__ void __launch_bounds__(ARCHE_BLOCK) __attribute__((amdgpu_waves_per_e
 // [group_begin[s], group_begin[s+1]) (its group), converged systems drop out.
 __global__ void __launch_bounds__(ARCHE_BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_scf_active_batch(const ActiveArgs* __restrict__ args, const int* __restrict__ group_begin, int nsys) {
-  __shared__ double sh[ARCHE_BLOCK / 64];
+  __shared__ double sh[RED_SH];
   __shared__ double r[8];
   __shared__ FdLds fdl;
   int s = 0;

@@ -45,6 +45,31 @@ def test_fermi_dirac_kernel(torch_cuda):
         assert rel.max() <= 5e-15, (name, x[m][np.argmax(rel)], rel.max())
 
 
+def test_fermi_dirac_derivatives(torch_cuda):
+    """The SCF kernel's I_{1/2} and derivatives: the first is I_{-1/2}/2 exactly
+    (dI_j/dx = j I_{j-1}); the second and third against central differences of
+    the oracle's I_{-1/2}/2 (step 1e-3: truncation about 1e-7 and 1e-5 relative);
+    across all three regimes and their seams."""
+    torch = torch_cuda
+    rng = np.random.default_rng(8)
+    x = np.concatenate([rng.uniform(-30, 100, 6000), rng.uniform(-3, 62, 6000),
+                        np.array([-2.0, -2.0 + 1e-12, -2.0 - 1e-12, 60.0, 60.0 - 1e-12, 0.0, -1.5])])
+    say("fd derivs n=%d" % x.size)
+    d = [t.cpu().numpy() for t in arche.fermi_dirac_derivs(torch.from_numpy(x).cuda())]
+    ref = ofd.fd_integrals(x)
+    h = 1e-3
+    rp, rm = ofd.fd_integrals(x + h), ofd.fd_integrals(x - h)
+    half = 0.5 * ref["m12"]
+    assert np.max(np.abs(d[0] / ref["p12"] - 1)) <= 5e-15
+    assert np.max(np.abs(d[1] / half - 1)) <= 5e-15
+    r2 = 0.5 * (rp["m12"] - rm["m12"]) / (2 * h)
+    r3 = 0.5 * (rp["m12"] - 2 * ref["m12"] + rm["m12"]) / h ** 2
+    e2 = np.abs(d[2] - r2) / (np.abs(r2) + 1e-6 * half)
+    e3 = np.abs(d[3] - r3) / (np.abs(r3) + 1e-6 * half)
+    say("d2 %.2e d3 %.2e" % (e2.max(), e3.max()))
+    assert e2.max() <= 1e-6 and e3.max() <= 1e-4
+
+
 FFT_SHAPES = [(16, 16, 16), (32, 32, 32), (20, 24, 30), (48, 50, 54), (60, 64, 72), (128, 128, 128), (12, 18, 10),
               (192, 96, 40)]
 
