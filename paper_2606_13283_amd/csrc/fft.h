@@ -96,7 +96,17 @@ struct ZArgs {
 
 // One pass of a compile-time transform: what a single-grid launch takes, and the
 // job a batched launch runs for one grid.
-enum { FFT_PASS_STRIDED = 0, FFT_PASS_Z_R2C = 1, FFT_PASS_Z_C2R = 2 };
+// FFT_PASS_ZY_R2C / FFT_PASS_YZ_C2R: the z and y passes of a grid with N_y = N_z
+// fused into one pass over x planes held in LDS (ZArgs; one block per plane);
+// FFT_PASS_NOP: the slot the fused pass frees (launches nothing).
+enum {
+  FFT_PASS_STRIDED = 0,
+  FFT_PASS_Z_R2C = 1,
+  FFT_PASS_Z_C2R = 2,
+  FFT_PASS_ZY_R2C = 3,
+  FFT_PASS_YZ_C2R = 4,
+  FFT_PASS_NOP = 5
+};
 struct FftPass {
   int kind;        // FFT_PASS_*
   int L;           // line length
@@ -107,7 +117,9 @@ struct FftPass {
   ZArgs z;         // the z passes
 };
 // The three passes of a fused transform (fft_r2c_fused / fft_c2r_fused with the
-// same arguments); false if the plan has no compile-time kernels.
+// same arguments); false if the plan has no compile-time kernels.  With plane
+// passes (fft_plane_fusable) the z and y passes are one and the other slot is a
+// FFT_PASS_NOP.
 bool fft_r2c_passes(const FftPlan* p, const double* in, cplx* out, double in_scale, double out_scale, int fin, int fout,
                     const FftFuse& f, FftPass out3[3]);
 bool fft_c2r_passes(const FftPlan* p, const cplx* in, cplx* work, double* out, double out_scale, int fin, int fout,
@@ -133,6 +145,8 @@ hipError_t fft_batch_launch(int kind, int sign, int mode, const FftPass* jobs, c
                             unsigned nblocks, hipStream_t s);
 
 bool fft_fusable(const FftPlan* p);
+// N_y = N_z with a plane kernel for that length (the plane fits in LDS)
+bool fft_plane_fusable(const FftPlan* p);
 // number of blocks (= partial sums) of the fused x pass and of the fused z pass
 int fft_x_blocks(const FftPlan* p);
 int fft_z_blocks(const FftPlan* p);

@@ -285,6 +285,59 @@ __global__ void __launch_bounds__(NT) k_z_c2r_ct(ZArgs A) {
   z_c2r_body<L, B, FOUT, NT>(A, blockIdx.x, lds, tw, sh);
 }
 
+// Plane passes (N_y = N_z = L): one block of PLANE_NT threads per x plane.
+constexpr int PLANE_NT = 1024;
+template <int L, int FIN>
+__global__ void __launch_bounds__(PLANE_NT) k_zy_r2c(ZArgs A) {
+  if (fft_stopped(A.f)) return;
+  __shared__ cplx plane[plane_elems<L>()];
+  __shared__ cplx tw[L];
+  zy_r2c_body<L, FIN, PLANE_NT>(A, blockIdx.x, plane, tw);
+}
+template <int L, int FOUT>
+__global__ void __launch_bounds__(PLANE_NT) k_yz_c2r(ZArgs A) {
+  if (fft_stopped(A.f)) return;
+  __shared__ cplx plane[plane_elems<L>()];
+  __shared__ cplx tw[L];
+  __shared__ double sh[PLANE_NT / 64];
+  yz_c2r_body<L, FOUT, PLANE_NT>(A, blockIdx.x, plane, tw, sh);
+}
+#define ARCHE_PLANE_SIZES(X) X(128)
+bool plane_supported(int L) {
+  switch (L) {
+#define X(n) case n:
+    ARCHE_PLANE_SIZES(X)
+#undef X
+    return true;
+    default:
+      return false;
+  }
+}
+template <int L>
+hipError_t launch_plane_L(const FftPass& ps, hipStream_t s) {
+  const dim3 grid(ps.nblocks), blk(PLANE_NT);
+  if (ps.kind == FFT_PASS_ZY_R2C) {
+    if (ps.mode == 0) hipLaunchKernelGGL((k_zy_r2c<L, 0>), grid, blk, 0, s, ps.z);
+    else if (ps.mode == 1) hipLaunchKernelGGL((k_zy_r2c<L, 1>), grid, blk, 0, s, ps.z);
+    else hipLaunchKernelGGL((k_zy_r2c<L, 2>), grid, blk, 0, s, ps.z);
+  } else {
+    if (ps.mode == 0) hipLaunchKernelGGL((k_yz_c2r<L, 0>), grid, blk, 0, s, ps.z);
+    else hipLaunchKernelGGL((k_yz_c2r<L, 1>), grid, blk, 0, s, ps.z);
+  }
+  return hipGetLastError();
+}
+hipError_t launch_plane(const FftPass& ps, hipStream_t s) {
+  switch (ps.L) {
+#define X(n) \
+  case n:    \
+    return launch_plane_L<n>(ps, s);
+    ARCHE_PLANE_SIZES(X)
+#undef X
+    default:
+      return hipErrorNotSupported;
+  }
+}
+
 // Tile variants (autotuned per line length, fft.h): strided passes take TK
 // columns per block with NT threads, z passes B row pairs with NT threads.
 // Variant 0 is the default; line lengths of the batched set use only it.
@@ -361,6 +414,8 @@ bool ct_supported(int L) {
 }
 
 hipError_t launch_pass_any(const FftPass& ps, hipStream_t s) {
+  if (ps.kind == FFT_PASS_NOP) return hipSuccess;
+  if (ps.kind == FFT_PASS_ZY_R2C || ps.kind == FFT_PASS_YZ_C2R) return launch_plane(ps, s);
   switch (ps.L) {
 #define X(n) \
   case n:    \
@@ -411,6 +466,24 @@ FftPass z_desc(int kind, int L, int code, const void* in, void* out, const cplx*
   const int B = ct_z_rows(L, ps.var);
   ps.nblocks = (unsigned)((npairs + B - 1) / B);
   ps.z = ZArgs{in, out, tw, npairs, is, os, f};
+  return ps;
+}
+
+// the fused z + y pass over the Nx planes of a grid with N_y = N_z = L
+FftPass plane_desc(int kind, int L, int code, const void* in, void* out, const cplx* tw, int nplanes, double is,
+                   double os, const FftFuse& f) {
+  FftPass ps{};
+  ps.kind = kind;
+  ps.L = L;
+  ps.sign = kind == FFT_PASS_ZY_R2C ? -1 : +1;
+  ps.mode = code;
+  ps.nblocks = (unsigned)nplanes;
+  ps.z = ZArgs{in, out, tw, (int64_t)nplanes * L / 2, is, os, f};
+  return ps;
+}
+FftPass nop_desc() {
+  FftPass ps{};
+  ps.kind = FFT_PASS_NOP;
   return ps;
 }
 
@@ -536,6 +609,15 @@ void fft_plan_destroy(FftPlan* plan) {
 
 hipError_t fft_r2c(const FftPlan* p, const double* in, cplx* out, double in_scale, double out_scale,
                    hipStream_t s) {
+  if (fft_plane_fusable(p)) {
+    {
+      ProfScope prof(PROF_FFT_Z, s);
+      hipError_t e0 = launch_plane(
+          plane_desc(FFT_PASS_ZY_R2C, p->N[2], 0, in, out, p->ax[2].tw, p->N[0], in_scale, 1.0, FftFuse{}), s);
+      if (e0 != hipSuccess) return e0;
+    }
+    return strided_pass(p, out, 0, -1, out_scale, s);
+  }
   const FftAxis& az = p->ax[2];
   const int Nz = p->N[2];
   const int64_t npairs = (int64_t)p->N[0] * p->N[1] / 2;
@@ -560,6 +642,11 @@ hipError_t fft_r2c(const FftPlan* p, const double* in, cplx* out, double in_scal
 hipError_t fft_c2r(const FftPlan* p, cplx* in, double* out, double out_scale, hipStream_t s) {
   hipError_t e = strided_pass(p, in, 0, +1, 1.0, s);
   if (e != hipSuccess) return e;
+  if (fft_plane_fusable(p)) {
+    ProfScope prof(PROF_FFT_Z, s);
+    return launch_plane(
+        plane_desc(FFT_PASS_YZ_C2R, p->N[2], 0, in, out, p->ax[2].tw, p->N[0], 1.0, out_scale, FftFuse{}), s);
+  }
   e = strided_pass(p, in, 1, +1, 1.0, s);
   if (e != hipSuccess) return e;
   const FftAxis& az = p->ax[2];
@@ -583,7 +670,11 @@ int fft_x_blocks(const FftPlan* p) {
   const int tk = kStridedTK[p->N[0] <= 1024 ? g_tile_var[1][p->N[0]] : 0];
   return p->N[1] * ((p->Nh + tk - 1) / tk);
 }
+bool fft_plane_fusable(const FftPlan* p) {
+  return fft_fusable(p) && p->N[1] == p->N[2] && plane_supported(p->N[2]);
+}
 int fft_z_blocks(const FftPlan* p) {
+  if (fft_plane_fusable(p)) return p->N[0];
   const int64_t npairs = (int64_t)p->N[0] * p->N[1] / 2;
   const int B = ct_z_rows(p->N[2], g_tile_var[2][p->N[2]]);
   return B ? (int)((npairs + B - 1) / B) : 0;
@@ -598,9 +689,14 @@ bool fft_r2c_passes(const FftPlan* p, const double* in, cplx* out, double in_sca
   if (!fft_fusable(p)) return false;
   const int64_t npairs = (int64_t)p->N[0] * p->N[1] / 2;
   const int Nh = p->Nh;
-  o[0] = z_desc(FFT_PASS_Z_R2C, p->N[2], fin, in, out, p->ax[2].tw, npairs, in_scale, 1.0, f);
-  o[1] = strided_desc(p->N[1], 0, -1, out, out, p->ax[1].tw, Nh, (int64_t)p->N[1] * Nh, p->N[0], Nh, 1.0, f, XGeom{},
-                      1);
+  if (fft_plane_fusable(p)) {
+    o[0] = plane_desc(FFT_PASS_ZY_R2C, p->N[2], fin, in, out, p->ax[2].tw, p->N[0], in_scale, 1.0, f);
+    o[1] = nop_desc();
+  } else {
+    o[0] = z_desc(FFT_PASS_Z_R2C, p->N[2], fin, in, out, p->ax[2].tw, npairs, in_scale, 1.0, f);
+    o[1] = strided_desc(p->N[1], 0, -1, out, out, p->ax[1].tw, Nh, (int64_t)p->N[1] * Nh, p->N[0], Nh, 1.0, f,
+                        XGeom{}, 1);
+  }
   const int mode = fout == R2C_OUT_LAP ? 1 : (fout == R2C_OUT_UH ? 2 : 0);
   o[2] = strided_desc(p->N[0], mode, -1, out, out, p->ax[0].tw, (int64_t)p->N[1] * Nh, Nh, p->N[1], Nh, out_scale, f,
                       xgeom(p, f), 0);
@@ -614,13 +710,19 @@ bool fft_c2r_passes(const FftPlan* p, const cplx* in, cplx* work, double* out, d
   const int Nh = p->Nh;
   o[0] = strided_desc(p->N[0], fin == C2R_IN_MIX ? 3 : 0, +1, work, fin == C2R_IN_MIX ? in : work, p->ax[0].tw,
                       (int64_t)p->N[1] * Nh, Nh, p->N[1], Nh, 1.0, f, xgeom(p, f), 0);
-  o[1] = strided_desc(p->N[1], 0, +1, work, work, p->ax[1].tw, Nh, (int64_t)p->N[1] * Nh, p->N[0], Nh, 1.0, f, XGeom{},
-                      1);
-  o[2] = z_desc(FFT_PASS_Z_C2R, p->N[2], fout, work, out, p->ax[2].tw, npairs, 1.0, out_scale, f);
+  if (fft_plane_fusable(p)) {
+    o[1] = nop_desc();
+    o[2] = plane_desc(FFT_PASS_YZ_C2R, p->N[2], fout, work, out, p->ax[2].tw, p->N[0], 1.0, out_scale, f);
+  } else {
+    o[1] = strided_desc(p->N[1], 0, +1, work, work, p->ax[1].tw, Nh, (int64_t)p->N[1] * Nh, p->N[0], Nh, 1.0, f,
+                        XGeom{}, 1);
+    o[2] = z_desc(FFT_PASS_Z_C2R, p->N[2], fout, work, out, p->ax[2].tw, npairs, 1.0, out_scale, f);
+  }
   return true;
 }
 
 hipError_t fft_pass_launch(const FftPass& ps, hipStream_t s) {
+  if (ps.kind == FFT_PASS_NOP) return hipSuccess;
   ProfScope prof(ps.kind == FFT_PASS_STRIDED ? PROF_FFT_STRIDED : PROF_FFT_Z, s);
   return launch_pass_any(ps, s);
 }

@@ -115,6 +115,7 @@ bool fft_batch_supported(int L) {
 
 hipError_t fft_batch_launch(int kind, int sign, int mode, const FftPass* jobs, const int* bbeg, int njobs,
                             unsigned nblocks, hipStream_t s) {
+  if (kind == FFT_PASS_NOP) return hipSuccess;
   if (njobs <= 0 || nblocks == 0) return hipSuccess;
   const dim3 grid(nblocks), blk(ARCHE_BLOCK);
   if (kind == FFT_PASS_STRIDED) {

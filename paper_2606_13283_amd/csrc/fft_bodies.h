@@ -293,3 +293,96 @@ constexpr int ct_rows() {
 }
 
 }  // namespace fftct
+
+namespace fftct {
+
+// ---------------------------------------------------------------------------
+// Plane passes for grids with N_y = N_z = L: one block per x plane holds the
+// whole plane (L x (L/2+1) complex) in LDS, so the z and y transforms of a 3D
+// transform run in one pass that reads and writes the plane once.
+
+template <int L>
+constexpr int plane_elems() {
+  return L * (L / 2 + 1);
+}
+
+struct PlaneOut {  // element (k_y = k, k_z = line) of the plane in global memory
+  cplx* base;
+  int nh;
+  double scale;
+  __device__ void operator()(int line, int k, cplx v) const { base[(int64_t)k * nh + line] = cscale(v, scale); }
+  __device__ void barrier_before() const {}
+  __device__ void barrier_after() const {}
+};
+
+// R2C: z transform of the plane's L/2 row pairs (input transform FIN as in the z
+// pass), Hermitian split into the [k_y][k_z] plane in LDS, y transform, store.
+template <int L, int FIN, int NT>
+__device__ inline void zy_r2c_body(const ZArgs& A, unsigned bid, cplx* plane, cplx* tw) {
+  constexpr int Nh = L / 2 + 1;
+  constexpr int NP = L / 2;
+  static_assert(NP * (L + 1) <= plane_elems<L>(), "packed rows fit the plane");
+  for (int i = threadIdx.x; i < L; i += NT) tw[i] = A.tw[i];
+  __syncthreads();
+  const int64_t off = (int64_t)bid * L * L;
+  const double* in = (const double*)A.in + off;
+  LdsIO<L, NP, false> packed{plane};
+  if constexpr (FIN == 0)
+    run<L, NP, NT, false, -1, 1>(PairIn{in, L, NP, A.in_scale}, packed, plane, tw, NP, typename Plan<L>::R{});
+  else if constexpr (FIN == 1)
+    run<L, NP, NT, false, -1, 1>(PairInSqrt{in, L, NP, A.in_scale}, packed, plane, tw, NP, typename Plan<L>::R{});
+  else
+    run<L, NP, NT, false, -1, 1>(PairInMix{in, A.f.n_i + off, L, NP, A.in_scale, *A.f.w}, packed, plane, tw, NP,
+                                 typename Plan<L>::R{});
+  // split pair l into rows 2l, 2l+1 (read everything, then overwrite in place)
+  constexpr int NOUT = L * Nh;
+  constexpr int PER = (NOUT + NT - 1) / NT;
+  cplx v[PER];
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int q = threadIdx.x + NT * p;
+    if (q < NOUT) {
+      const int y = q / Nh, k = q - (q / Nh) * Nh;
+      const cplx zk = packed(y >> 1, k);
+      const cplx zn = packed(y >> 1, k == 0 ? 0 : L - k);
+      v[p] = (y & 1) ? cplx{0.5 * (zk.y + zn.y), -0.5 * (zk.x - zn.x)} : cplx{0.5 * (zk.x + zn.x), 0.5 * (zk.y - zn.y)};
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int q = threadIdx.x + NT * p;
+    if (q < NOUT) plane[q] = v[p];
+  }
+  __syncthreads();
+  run<L, Nh, NT, true, -1, 1>(LdsIO<L, Nh, true>{plane}, PlaneOut{(cplx*)A.out + (int64_t)bid * NOUT, Nh, A.out_scale},
+                              plane, tw, Nh, typename Plan<L>::R{});
+}
+
+// C2R: y transform of the plane into LDS, then the z transform of its row pairs
+// (output transform FOUT as in the z pass).
+template <int L, int FOUT, int NT>
+__device__ inline void yz_c2r_body(const ZArgs& A, unsigned bid, cplx* plane, cplx* tw, double* sh) {
+  constexpr int Nh = L / 2 + 1;
+  constexpr int NP = L / 2;
+  for (int i = threadIdx.x; i < L; i += NT) tw[i] = A.tw[i];
+  __syncthreads();
+  const cplx* in = (const cplx*)A.in + (int64_t)bid * L * Nh;
+  LdsIO<L, Nh, true> pl{plane};
+  run<L, Nh, NT, true, +1, 1>(ColIn{in, Nh, Nh}, pl, plane, tw, Nh, typename Plan<L>::R{});
+  const int64_t off = (int64_t)bid * L * L;
+  if constexpr (FOUT == 0) {
+    run<L, NP, NT, false, +1, 1>(HermIn{plane, L, Nh, NP}, PairOut{(double*)A.out + off, L, NP, A.out_scale}, plane,
+                                 tw, NP, typename Plan<L>::R{});
+  } else {
+    double acc = 0.0;
+    run<L, NP, NT, false, +1, 1>(
+        HermIn{plane, L, Nh, NP},
+        PairOutUvw{A.f.n_i + off, A.f.lap_i + off, A.f.n_a + off, L, NP, A.out_scale, 0.5 * A.f.lam, &acc}, plane, tw,
+        NP, typename Plan<L>::R{});
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) A.f.partials[bid] = acc;
+  }
+}
+
+}  // namespace fftct
