@@ -110,6 +110,8 @@ struct IterStep {
   int slot, kind;
   unsigned nblocks;
   FftPass fft;
+  int dual;     // STEP_FFT: fft and fft2 are independent and launched together
+  FftPass fft2;
   MixWeightArgs mw;
   RealMixArgs rm;
 };

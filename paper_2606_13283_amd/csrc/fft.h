@@ -125,6 +125,9 @@ bool fft_r2c_passes(const FftPlan* p, const double* in, cplx* out, double in_sca
 bool fft_c2r_passes(const FftPlan* p, const cplx* in, cplx* work, double* out, double out_scale, int fin, int fout,
                     const FftFuse& f, FftPass out3[3]);
 hipError_t fft_pass_launch(const FftPass& ps, hipStream_t s);
+// Two independent passes in one launch (the blocks of a, then those of b) where a
+// combined kernel exists, else one after the other.
+hipError_t fft_dual_launch(const FftPass& a, const FftPass& b, hipStream_t s);
 
 // Tile autotuner: for each line length of the plan outside the batched set,
 // time the tile variants of the y, x and z passes on the scratch arrays (any

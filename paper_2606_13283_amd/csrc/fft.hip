@@ -338,6 +338,44 @@ hipError_t launch_plane(const FftPass& ps, hipStream_t s) {
   }
 }
 
+// Two independent plane passes in one launch: blocks [0, n1) run the first
+// (direction K1: 0 R2C z+y, 1 C2R y+z; mode M1), the rest the second, so the
+// pair fills the CUs that one pass over Nx planes leaves idle.
+template <int L, int K, int M>
+__device__ inline void plane_body(const ZArgs& A, unsigned bid, cplx* plane, cplx* tw, double* sh) {
+  if constexpr (K == 0)
+    zy_r2c_body<L, M, PLANE_NT>(A, bid, plane, tw);
+  else
+    yz_c2r_body<L, M, PLANE_NT>(A, bid, plane, tw, sh);
+}
+template <int L, int K1, int M1, int K2, int M2>
+__global__ void __launch_bounds__(PLANE_NT) k_plane_dual(ZArgs A, ZArgs B, unsigned n1) {
+  __shared__ cplx plane[plane_elems<L>()];
+  __shared__ cplx tw[L];
+  __shared__ double sh[PLANE_NT / 64];
+  if (blockIdx.x < n1) {
+    if (fft_stopped(A.f)) return;
+    plane_body<L, K1, M1>(A, blockIdx.x, plane, tw, sh);
+  } else {
+    if (fft_stopped(B.f)) return;
+    plane_body<L, K2, M2>(B, blockIdx.x - n1, plane, tw, sh);
+  }
+}
+// The same for two strided passes of one line length and tile.
+template <int L, int TK, int S1, int M1, int S2, int M2, int NT>
+__global__ void __launch_bounds__(NT) k_strided_dual(StridedArgs A, StridedArgs B, unsigned n1) {
+  __shared__ cplx lds[strided_lds<L, TK>()];
+  __shared__ cplx tw[L];
+  __shared__ double sh[NT / 64];
+  if (blockIdx.x < n1) {
+    if (fft_stopped(A.f)) return;
+    strided_body<L, TK, S1, M1, NT>(A, blockIdx.x, lds, tw, sh);
+  } else {
+    if (fft_stopped(B.f)) return;
+    strided_body<L, TK, S2, M2, NT>(B, blockIdx.x - n1, lds, tw, sh);
+  }
+}
+
 // Tile variants (autotuned per line length, fft.h): strided passes take TK
 // columns per block with NT threads, z passes B row pairs with NT threads.
 // Variant 0 is the default; line lengths of the batched set use only it.
@@ -411,6 +449,32 @@ bool ct_supported(int L) {
     default:
       return false;
   }
+}
+
+// direction code of a plane pass (0 R2C, 1 C2R), -1 otherwise
+int plane_dir(const FftPass& p) {
+  return p.kind == FFT_PASS_ZY_R2C ? 0 : (p.kind == FFT_PASS_YZ_C2R ? 1 : -1);
+}
+
+// The pairs the SCF iteration launches together: R2C(n_a) with R2C(sqrt n_a)
+// (plane and x passes), and the Hartree C2R's plane pass with R2C(sqrt n_o)'s.
+template <int L>
+bool launch_dual_L(const FftPass& a, const FftPass& b, hipStream_t s, hipError_t* e) {
+  const dim3 blk_p(PLANE_NT);
+  const int da = plane_dir(a), db = plane_dir(b);
+  if (da == 0 && a.mode == 0 && db == 0 && b.mode == 1) {
+    hipLaunchKernelGGL((k_plane_dual<L, 0, 0, 0, 1>), dim3(a.nblocks + b.nblocks), blk_p, 0, s, a.z, b.z, a.nblocks);
+  } else if (da == 1 && a.mode == 0 && db == 0 && b.mode == 2) {
+    hipLaunchKernelGGL((k_plane_dual<L, 1, 0, 0, 2>), dim3(a.nblocks + b.nblocks), blk_p, 0, s, a.z, b.z, a.nblocks);
+  } else if (a.kind == FFT_PASS_STRIDED && b.kind == FFT_PASS_STRIDED && a.var == 0 && b.var == 0 && a.sign < 0 &&
+             b.sign < 0 && a.mode == 2 && b.mode == 1) {
+    hipLaunchKernelGGL((k_strided_dual<L, kStridedTK[0], -1, 2, -1, 1, kStridedNT[0]>), dim3(a.nblocks + b.nblocks),
+                       dim3(kStridedNT[0]), 0, s, a.s, b.s, a.nblocks);
+  } else {
+    return false;
+  }
+  *e = hipGetLastError();
+  return true;
 }
 
 hipError_t launch_pass_any(const FftPass& ps, hipStream_t s) {
@@ -719,6 +783,16 @@ bool fft_c2r_passes(const FftPlan* p, const cplx* in, cplx* work, double* out, d
     o[2] = z_desc(FFT_PASS_Z_C2R, p->N[2], fout, work, out, p->ax[2].tw, npairs, 1.0, out_scale, f);
   }
   return true;
+}
+
+hipError_t fft_dual_launch(const FftPass& a, const FftPass& b, hipStream_t s) {
+  if (a.L == b.L && a.L == 128 && plane_supported(128)) {
+    ProfScope prof(plane_dir(a) >= 0 ? PROF_FFT_Z : PROF_FFT_STRIDED, s);
+    hipError_t e = hipSuccess;
+    if (launch_dual_L<128>(a, b, s, &e)) return e;
+  }
+  hipError_t e = fft_pass_launch(a, s);
+  return e == hipSuccess ? fft_pass_launch(b, s) : e;
 }
 
 hipError_t fft_pass_launch(const FftPass& ps, hipStream_t s) {

@@ -698,6 +698,25 @@ static ActiveArgs active_args(const arche_ctx* c) {
   return a;
 }
 
+static void push_pass(std::vector<IterStep>& v, int slot, const FftPass& a) {
+  IterStep st{};
+  st.slot = slot;
+  st.kind = STEP_FFT;
+  st.fft = a;
+  st.nblocks = a.nblocks;
+  v.push_back(st);
+}
+static void push_dual(std::vector<IterStep>& v, int slot, const FftPass& a, const FftPass& b) {
+  IterStep st{};
+  st.slot = slot;
+  st.kind = STEP_FFT;
+  st.fft = a;
+  st.fft2 = b;
+  st.dual = 1;
+  st.nblocks = a.nblocks + b.nblocks;
+  v.push_back(st);
+}
+
 static void push_fft(std::vector<IterStep>& v, int slot, const FftPass* ps) {
   for (int i = 0; i < 3; ++i) {
     IterStep st{};
@@ -742,10 +761,25 @@ void scf_build_iteration(arche_ctx* c) {
   f.L[2] = g.L[2];
   f.partials = part_h;
   f.stop = &c->state->done;
+  // With plane passes (N_y = N_z) independent transforms share launches: the
+  // plane and x passes of R2C(n_a) and R2C(sqrt n_a), and the Hartree C2R's plane
+  // pass with that of R2C(sqrt n_o), which then works in ctmp2.
+  const bool pair = fft_plane_fusable(&c->plan);
   FftPass ps[3];
   fft_r2c_passes(&c->plan, c->n_a, c->nhat_a, 1.0, g.dv, FUSE_NONE, R2C_OUT_UH, f, ps);
-  push_fft(c->steps, SLOT_NHAT_A, ps);
-  if (more && vw) {
+  if (pair && more && vw) {
+    FftPass pb[3];
+    fft_r2c_passes(&c->plan, c->n_a, c->ctmp, 1.0, g.dv, R2C_IN_SQRT, R2C_OUT_LAP, f, pb);
+    push_dual(c->steps, SLOT_NHAT_A, ps[0], pb[0]);
+    push_dual(c->steps, SLOT_NHAT_A + 2, ps[2], pb[2]);
+    FftFuse fv = f;
+    fv.partials = part_v;
+    fft_c2r_passes(&c->plan, c->ctmp, c->ctmp, nullptr, 1.0 / g.vol, FUSE_NONE, C2R_OUT_UVW, fv, ps);
+    push_fft(c->steps, SLOT_UVW, ps);
+  } else {
+    push_fft(c->steps, SLOT_NHAT_A, ps);
+  }
+  if (more && vw && !pair) {
     fft_r2c_passes(&c->plan, c->n_a, c->ctmp, 1.0, g.dv, R2C_IN_SQRT, R2C_OUT_LAP, f, ps);
     push_fft(c->steps, SLOT_LAP_A, ps);
     FftFuse fv = f;
@@ -759,6 +793,17 @@ void scf_build_iteration(arche_ctx* c) {
   w.nblocks = 1;
   w.mw = MixWeightArgs{c->state, part_h, nbh, part_v, nbv, (int)(more && vw), g.vol, g.dv, p.w_fixed};
   c->steps.push_back(w);
+  if (pair && vw) {
+    FftPass pe[3], pf[3];
+    fft_c2r_passes(&c->plan, c->nhat_a, c->ctmp, c->VH, 1.0 / g.vol, C2R_IN_MIX, FUSE_NONE, f, pe);
+    fft_r2c_passes(&c->plan, c->n_a, c->ctmp2, 1.0, g.dv, R2C_IN_MIX_SQRT, R2C_OUT_LAP, f, pf);
+    push_pass(c->steps, SLOT_HARTREE, pe[0]);
+    push_dual(c->steps, SLOT_HARTREE + 2, pe[2], pf[0]);
+    push_pass(c->steps, SLOT_SQRT_O + 2, pf[2]);
+    fft_c2r_passes(&c->plan, c->ctmp2, c->ctmp2, c->lap_i, 1.0 / g.vol, FUSE_NONE, FUSE_NONE, f, ps);
+    push_fft(c->steps, SLOT_LAP_O, ps);
+    return;
+  }
   fft_c2r_passes(&c->plan, c->nhat_a, c->ctmp, c->VH, 1.0 / g.vol, C2R_IN_MIX, FUSE_NONE, f, ps);
   push_fft(c->steps, SLOT_HARTREE, ps);
   if (vw) {
@@ -779,7 +824,7 @@ void scf_build_iteration(arche_ctx* c) {
 unsigned scf_real_mix_blocks(int64_t ng) { return grid_for(ng); }
 
 hipError_t scf_step_launch(const IterStep& st, hipStream_t s) {
-  if (st.kind == STEP_FFT) return fft_pass_launch(st.fft, s);
+  if (st.kind == STEP_FFT) return st.dual ? fft_dual_launch(st.fft, st.fft2, s) : fft_pass_launch(st.fft, s);
   if (st.kind == STEP_WEIGHT)
     hipLaunchKernelGGL(k_mix_weight, dim3(1), dim3(ARCHE_BLOCK), 0, s, st.mw);
   else
