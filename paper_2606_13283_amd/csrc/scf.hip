@@ -13,8 +13,11 @@ namespace {
 constexpr double PI = 3.14159265358979323846;
 
 
-// The grid is cut into chunks of SCF_CHUNK consecutive points; thread t of the
-// block that owns a chunk handles points t + ARCHE_BLOCK*q, q < PPT.  Every
+// The grid is cut into nchunk chunks of SCF_CHUNK points: the grid is read as
+// PPT stripes of nchunk*ARCHE_BLOCK points, and chunk c takes the c-th run of
+// ARCHE_BLOCK consecutive points in each stripe (thread t the t-th of each).  A
+// chunk thus samples the whole cell, and blocks near ions and between them carry
+// the same mix of work; each wave still reads 64 consecutive values.  Every
 // global sum is a sum of per-chunk partials in chunk order, so the result does
 // not depend on how many blocks share the work (a batched solve, with fewer
 // blocks per snapshot, is bit-identical to an unbatched one).
@@ -34,12 +37,54 @@ constexpr double SPEC_NEWTON = 1e-7;
 // LDS doubles for block_reduce_n<8>
 constexpr int RED_SH = (ARCHE_BLOCK / 64) * 8;
 
+// point q of this thread in chunk c (>= ng: none)
+__device__ inline int64_t chunk_point(const ActiveArgs& a, int64_t c, int q) {
+  return (int64_t)q * (a.nchunk * ARCHE_BLOCK) + c * ARCHE_BLOCK + threadIdx.x;
+}
+
 // The first NV block-reduced values of acc go to slots s0.. of chunk c.
 template <int NV>
 __device__ inline void put_chunk_n(const double* acc, double* part, int s0, int64_t nchunk, int64_t c) {
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) coherent_store(part + (int64_t)(s0 + k) * nchunk + c, acc[k]);  // read by grid_allreduce
+  }
+}
+
+// Points are processed in groups of PG: the group's loads are issued together
+// (at indices clamped into the grid, so a ragged tail needs no branch), the
+// common paths (the interval polynomial of I_{1/2}, the r_s >= 1 branch of the
+// LDA, the cubic K shift) run branch-free so the points' evaluations interleave,
+// and the rare cases are redone for the lanes that need them.
+constexpr int PG = 2;
+
+// I_{1/2} and D derivatives at x[g] for a group
+template <int D>
+__device__ inline void fd_group(const FdLds& fdl, const double* x, double (*d)[D + 1]) {
+#pragma unroll
+  for (int g = 0; g < PG; ++g) fd_p12_poly<D>(fdl, x[g], d[g]);
+  bool out = false;
+#pragma unroll
+  for (int g = 0; g < PG; ++g) out |= !fd_p12_in_poly(x[g]);
+  if (out) {
+#pragma unroll
+    for (int g = 0; g < PG; ++g)
+      if (!fd_p12_in_poly(x[g])) fd_p12_derivs<D>(fdl, x[g], d[g]);
+  }
+}
+
+// v_xc(n[g]) for a group
+__device__ inline void vxc_group(const double* n, double* v) {
+  bool hi[PG], any = false;
+#pragma unroll
+  for (int g = 0; g < PG; ++g) {
+    v[g] = lda_vxc_low(n[g], hi[g]);
+    any |= hi[g];
+  }
+  if (any) {
+#pragma unroll
+    for (int g = 0; g < PG; ++g)
+      if (hi[g]) lda_xc(n[g], v[g]);
   }
 }
 
@@ -50,41 +95,78 @@ __device__ inline void put_chunk_n(const double* acc, double* part, int s0, int6
 //   slots 2..7: sum dn^2, sum n_a^2, K, U_xc, sum n_a, max |dn|/n_a
 //   (dn = n_i - n_a; K is the secant of the Thomas-Fermi potential kT eta(n)
 //   between n_a and n_i, U_xc the same for v_xc)
-// With CACHE, vreg and xreg hold this thread's V_i and v_xc(n_i) from the assembly.
+// With CACHE, vls and xls (LDS, [PPT][ARCHE_BLOCK]) hold the block's V_i and
+// v_xc(n_i) from the assembly.
 template <bool CACHE, bool ACTIVE>
-__device__ inline void chunk_sums(const ActiveArgs& a, int64_t c, const double* vreg, const double* xreg, double mu,
+__device__ inline void chunk_sums(const ActiveArgs& a, int64_t c, const double* vls, const double* xls, double mu,
                                   double ikT, const FdLds& fdl, double* sh) {
   const bool more = a.mixing == ARCHE_MIX_MORE;
   const double icn = 1.0 / a.cn;
+  constexpr int D = ACTIVE ? 3 : 1;
   double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int q = 0; q < PPT; ++q) {
-    const int64_t i = c * SCF_CHUNK + threadIdx.x + (int64_t)ARCHE_BLOCK * q;
-    if (i < a.ng) {
-      const double v = CACHE ? vreg[q] : a.Vi[i];
-      const double eta = (mu - v) * ikT;
-      double d[ACTIVE ? 4 : 2];
-      fd_p12_derivs<ACTIVE ? 3 : 1>(fdl, eta, d);
-      acc[0] += d[0];
-      acc[1] += d[1];
-      if (ACTIVE) {
-        const double na = a.cn * d[0];
-        const double ni = a.n_i[i];
-        const double dn = ni - na;
-        a.n_a[i] = na;
-        acc[2] += dn * dn;
-        acc[3] += na * na;
-        if (more) acc[4] += a.kT * fd_p12_shift(fdl, ni * icn, eta, d) * dn;  // kT (eta_i - eta_a) dn
-        if (a.xc) {
-          double vi, va;
-          if (CACHE)
-            vi = xreg[q];
-          else
-            lda_xc(ni, vi);
-          lda_xc(na, va);
-          acc[5] += (vi - va) * dn;
+#pragma unroll 1
+  for (int q0 = 0; q0 < PPT; q0 += PG) {
+    int64_t ip[PG];
+    bool ok[PG];
+    double x[PG], ni[PG];
+#pragma unroll
+    for (int g = 0; g < PG; ++g) {
+      const int64_t i = chunk_point(a, c, q0 + g);
+      ok[g] = i < a.ng;
+      ip[g] = ok[g] ? i : a.ng - 1;
+      const double v = CACHE ? vls[(q0 + g) * ARCHE_BLOCK + threadIdx.x] : a.Vi[ip[g]];
+      x[g] = (mu - v) * ikT;
+      if (ACTIVE) ni[g] = a.n_i[ip[g]];
+    }
+    double d[PG][D + 1];
+    fd_group<D>(fdl, x, d);
+#pragma unroll
+    for (int g = 0; g < PG; ++g) {
+      acc[0] += ok[g] ? d[g][0] : 0.0;
+      acc[1] += ok[g] ? d[g][1] : 0.0;
+    }
+    if (ACTIVE) {
+      double na[PG], dn[PG];
+#pragma unroll
+      for (int g = 0; g < PG; ++g) {
+        na[g] = a.cn * d[g][0];
+        dn[g] = ni[g] - na[g];
+        if (ok[g]) a.n_a[ip[g]] = na[g];
+        acc[2] += ok[g] ? dn[g] * dn[g] : 0.0;
+        acc[3] += ok[g] ? na[g] * na[g] : 0.0;
+      }
+      if (more) {
+        double sh_[PG];
+        bool far[PG], anyfar = false;
+#pragma unroll
+        for (int g = 0; g < PG; ++g) {
+          sh_[g] = fd_p12_shift_cubic(ni[g] * icn, d[g], far[g]);
+          anyfar |= far[g] && ok[g];
         }
-        acc[6] += na;
-        acc[7] = fmax(acc[7], fabs(dn) / na);
+        if (anyfar) {
+#pragma unroll
+          for (int g = 0; g < PG; ++g)
+            if (far[g] && ok[g]) sh_[g] = fd_p12_inverse_from(fdl, ni[g] * icn, x[g], d[g][0], d[g][1]) - x[g];
+        }
+#pragma unroll
+        for (int g = 0; g < PG; ++g) acc[4] += ok[g] ? a.kT * sh_[g] * dn[g] : 0.0;  // kT (eta_i - eta_a) dn
+      }
+      if (a.xc) {
+        double va[PG], vi[PG];
+        vxc_group(na, va);
+        if (CACHE) {
+#pragma unroll
+          for (int g = 0; g < PG; ++g) vi[g] = xls[(q0 + g) * ARCHE_BLOCK + threadIdx.x];
+        } else {
+          vxc_group(ni, vi);
+        }
+#pragma unroll
+        for (int g = 0; g < PG; ++g) acc[5] += ok[g] ? (vi[g] - va[g]) * dn[g] : 0.0;
+      }
+#pragma unroll
+      for (int g = 0; g < PG; ++g) {
+        acc[6] += ok[g] ? na[g] : 0.0;
+        acc[7] = ok[g] ? fmax(acc[7], fabs(dn[g]) / na[g]) : acc[7];
       }
     }
   }
@@ -107,16 +189,15 @@ __device__ inline void chunk_sums(const ActiveArgs& a, int64_t c, const double* 
 //   4. the SCF scalars (block 0)
 // grid_allreduce hands every block of the group the same fixed-order result, so
 // all of them take the same branches.  With CACHE (at most one chunk per block)
-// V_i and v_xc(n_i) stay in registers between the phases; V_i is stored only
-// by the iteration that ends the solve (the energies of Sec. 2.6 read it).
+// V_i and v_xc(n_i) stay in LDS between the phases; V_i is stored only by the
+// iteration that ends the solve (the energies of Sec. 2.6 read it).
 template <bool CACHE>
 __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigned G, const FdLds& fdl, double* sh,
-                                       double* r) {
+                                       double* r, double* vls, double* xls) {
   ScfState* st = a.st;
   unsigned* go = a.flags + G;
   unsigned epoch = (unsigned)(st->iter + 1) * 256u;  // grows by one per all-reduce; disjoint per launch
   const int64_t nchunk = a.nchunk;
-  double vreg[CACHE ? PPT : 1], xreg[CACHE ? PPT : 1];
   const double kT = a.kT;
   const double ikT = 1.0 / kT;
   const double mu_prev = st->mu;  // NaN on the first iteration
@@ -128,33 +209,50 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
   // 1. potential assembly (+ the Taylor sums of N at the previous mu)
   FOR_CHUNKS(c) {
     double acc[7] = {0.0, -INFINITY, -INFINITY, 0.0, 0.0, 0.0, 0.0};
-    for (int q = 0; q < PPT; ++q) {
-      const int64_t i = c * SCF_CHUNK + threadIdx.x + (int64_t)ARCHE_BLOCK * q;
-      if (i < a.ng) {
-        const double n = a.n_i[i];
-        double v = a.Vie[i] + a.VH[i];
-        double vxc = 0.0;
-        if (a.xc) {
-          lda_xc(n, vxc);
-          v += vxc;
-        }
-        if (a.lam != 0.0) v += -0.5 * a.lam * a.lap_i[i] / sqrt(n);
+#pragma unroll 1
+  for (int q0 = 0; q0 < PPT; q0 += PG) {
+      bool ok[PG];
+      double n[PG], v[PG], lp[PG], vx[PG];
+#pragma unroll
+      for (int g = 0; g < PG; ++g) {
+        const int64_t i = chunk_point(a, c, q0 + g);
+        ok[g] = i < a.ng;
+        const int64_t ic = ok[g] ? i : a.ng - 1;
+        n[g] = a.n_i[ic];
+        v[g] = a.Vie[ic] + a.VH[ic];
+        lp[g] = a.lap_i[ic];
+      }
+      if (a.xc) {
+        vxc_group(n, vx);
+      } else {
+#pragma unroll
+        for (int g = 0; g < PG; ++g) vx[g] = 0.0;
+      }
+#pragma unroll
+      for (int g = 0; g < PG; ++g) {
+        v[g] += vx[g];
+        if (a.lam != 0.0) v[g] += -0.5 * a.lam * lp[g] / sqrt(n[g]);
         if (CACHE) {
-          vreg[q] = v;
-          xreg[q] = vxc;
-        } else {
-          a.Vi[i] = v;
+          vls[(q0 + g) * ARCHE_BLOCK + threadIdx.x] = v[g];
+          xls[(q0 + g) * ARCHE_BLOCK + threadIdx.x] = vx[g];
+        } else if (ok[g]) {
+          a.Vi[chunk_point(a, c, q0 + g)] = v[g];
         }
-        acc[0] += v;
-        acc[1] = fmax(acc[1], v);
-        acc[2] = fmax(acc[2], -v);
-        if (try_prev) {
-          double d[4];
-          fd_p12_derivs<3>(fdl, (mu_prev - v) * ikT, d);
-          acc[3] += d[0];
-          acc[4] += d[1];
-          acc[5] += d[2];
-          acc[6] += d[3];
+        acc[0] += ok[g] ? v[g] : 0.0;
+        acc[1] = ok[g] ? fmax(acc[1], v[g]) : acc[1];
+        acc[2] = ok[g] ? fmax(acc[2], -v[g]) : acc[2];
+      }
+      if (try_prev) {
+        double x[PG], d[PG][4];
+#pragma unroll
+        for (int g = 0; g < PG; ++g) x[g] = (mu_prev - v[g]) * ikT;
+        fd_group<3>(fdl, x, d);
+#pragma unroll
+        for (int g = 0; g < PG; ++g) {
+          acc[3] += ok[g] ? d[g][0] : 0.0;
+          acc[4] += ok[g] ? d[g][1] : 0.0;
+          acc[5] += ok[g] ? d[g][2] : 0.0;
+          acc[6] += ok[g] ? d[g][3] : 0.0;
         }
       }
     }
@@ -214,10 +312,10 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
   while (!found && it < a.max_newton) {
     ++it;
     if (spec) {
-      FOR_CHUNKS(c) chunk_sums<CACHE, true>(a, c, vreg, xreg, mu, ikT, fdl, sh);
+      FOR_CHUNKS(c) chunk_sums<CACHE, true>(a, c, vls, xls, mu, ikT, fdl, sh);
       grid_allreduce(a.part, nchunk, a.res, 0, 8, 0x80u, G, lb, a.flags, go, ++epoch, a.err, r, sh);
     } else {
-      FOR_CHUNKS(c) chunk_sums<CACHE, false>(a, c, vreg, xreg, mu, ikT, fdl, sh);
+      FOR_CHUNKS(c) chunk_sums<CACHE, false>(a, c, vls, xls, mu, ikT, fdl, sh);
       grid_allreduce(a.part, nchunk, a.res, 0, 2, 0u, G, lb, a.flags, go, ++epoch, a.err, r, sh);
     }
     N = scale * r[0];
@@ -248,7 +346,7 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
 
   // 3. active density and the mixing reductions (unless the last pass formed them)
   if (!have_sums) {
-    FOR_CHUNKS(c) chunk_sums<CACHE, true>(a, c, vreg, xreg, mu, ikT, fdl, sh);
+    FOR_CHUNKS(c) chunk_sums<CACHE, true>(a, c, vls, xls, mu, ikT, fdl, sh);
     grid_allreduce(a.part, nchunk, a.res, 0, 8, 0x80u, G, lb, a.flags, go, ++epoch, a.err, r, sh);
     for (int k = 0; k < 6; ++k) D[k] = r[2 + k];
   }
@@ -260,8 +358,8 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
   if (CACHE && last) {
     FOR_CHUNKS(c) {
       for (int q = 0; q < PPT; ++q) {
-        const int64_t i = c * SCF_CHUNK + threadIdx.x + (int64_t)ARCHE_BLOCK * q;
-        if (i < a.ng) a.Vi[i] = vreg[q];
+        const int64_t i = chunk_point(a, c, q);
+        if (i < a.ng) a.Vi[i] = vls[q * ARCHE_BLOCK + threadIdx.x];
       }
     }
   }
@@ -297,10 +395,11 @@ __global__ void __launch_bounds__(ARCHE_BLOCK) __attribute__((amdgpu_waves_per_e
   __shared__ double sh[RED_SH];
   __shared__ double r[8];
   __shared__ FdLds fdl;
+  __shared__ double vls[CACHE ? PPT * ARCHE_BLOCK : 1], xls[CACHE ? PPT * ARCHE_BLOCK : 1];
   if (a.st->done) return;
   fd_lds_load(&fdl, a.fdt);
   __syncthreads();
-  scf_active_body<CACHE>(a, blockIdx.x, gridDim.x, fdl, sh, r);
+  scf_active_body<CACHE>(a, blockIdx.x, gridDim.x, fdl, sh, r, vls, xls);
 }
 
 // Many systems in one cooperative launch: system s owns blocks
@@ -310,6 +409,7 @@ k_scf_active_batch(const ActiveArgs* __restrict__ args, const int* __restrict__ 
   __shared__ double sh[RED_SH];
   __shared__ double r[8];
   __shared__ FdLds fdl;
+  __shared__ double vls[PPT * ARCHE_BLOCK], xls[PPT * ARCHE_BLOCK];
   int s = 0;
   while (s + 1 < nsys && group_begin[s + 1] <= (int)blockIdx.x) ++s;
   const ActiveArgs a = args[s];
@@ -319,9 +419,9 @@ k_scf_active_batch(const ActiveArgs* __restrict__ args, const int* __restrict__ 
   const unsigned lb = blockIdx.x - group_begin[s];
   const unsigned G = group_begin[s + 1] - group_begin[s];
   if ((int64_t)G >= a.nchunk)
-    scf_active_body<true>(a, lb, G, fdl, sh, r);
+    scf_active_body<true>(a, lb, G, fdl, sh, r, vls, xls);
   else
-    scf_active_body<false>(a, lb, G, fdl, sh, r);
+    scf_active_body<false>(a, lb, G, fdl, sh, r, vls, xls);
 }
 
 // U_vW = int (v_vW[n_i] - v_vW[n_a]) (n_i - n_a), v_vW[n] = -(lambda/2) lap(sqrt n)/sqrt n
