@@ -37,12 +37,14 @@ METRIC = "SCF iters/s + wall s per MD step (plain vs learned-init/batched), 1024
 def kernel_bytes(name, ng, nh, newton_per_launch):
     """Algorithmic HBM bytes of one launch of each timed kernel class."""
     if name == "scf_active":
-        # potential assembly: read n_i, V^ie, V_H, lap sqrt(n_i), write V_i (40 B/pt); the
-        # Newton passes read nothing (V_i stays in registers); the last phase reads n_i and
-        # writes n_a (16 B/pt)
-        return ng * 56.0
+        # potential assembly: read n_i, V^ie, V_H, lap sqrt(n_i) (32 B/pt); the Newton
+        # passes read nothing (V_i and v_xc(n_i) stay in LDS); the last phase reads n_i and
+        # writes n_a (16 B/pt); V_i is written only by the iteration that ends the solve
+        return ng * 48.0
     if name == "fft_z":
-        return ng * 8.0 + nh * 16.0  # real field in/out + half spectrum out/in
+        # the z pass, or on N_y = N_z grids the fused z+y plane pass: real field in/out +
+        # half spectrum out/in
+        return ng * 8.0 + nh * 16.0
     if name == "fft_strided":
         return 2.0 * nh * 16.0  # half spectrum read and written in place
     raise KeyError(name)

@@ -671,9 +671,12 @@ void fft_plan_destroy(FftPlan* plan) {
   std::memset(plan, 0, sizeof(*plan));
 }
 
+// the plane passes move the real field as 16-byte pairs
+static bool aligned16(const void* a, const void* b) { return (((uintptr_t)a | (uintptr_t)b) & 15u) == 0; }
+
 hipError_t fft_r2c(const FftPlan* p, const double* in, cplx* out, double in_scale, double out_scale,
                    hipStream_t s) {
-  if (fft_plane_fusable(p)) {
+  if (fft_plane_fusable(p) && aligned16(in, out)) {
     {
       ProfScope prof(PROF_FFT_Z, s);
       hipError_t e0 = launch_plane(
@@ -706,7 +709,7 @@ hipError_t fft_r2c(const FftPlan* p, const double* in, cplx* out, double in_scal
 hipError_t fft_c2r(const FftPlan* p, cplx* in, double* out, double out_scale, hipStream_t s) {
   hipError_t e = strided_pass(p, in, 0, +1, 1.0, s);
   if (e != hipSuccess) return e;
-  if (fft_plane_fusable(p)) {
+  if (fft_plane_fusable(p) && aligned16(in, out)) {
     ProfScope prof(PROF_FFT_Z, s);
     return launch_plane(
         plane_desc(FFT_PASS_YZ_C2R, p->N[2], 0, in, out, p->ax[2].tw, p->N[0], 1.0, out_scale, FftFuse{}), s);

@@ -315,25 +315,77 @@ struct PlaneOut {  // element (k_y = k, k_z = line) of the plane in global memor
   __device__ void barrier_after() const {}
 };
 
-// R2C: z transform of the plane's L/2 row pairs (input transform FIN as in the z
-// pass), Hermitian split into the [k_y][k_z] plane in LDS, y transform, store.
+// The real plane in LDS: row pair l (rows y = 2l, 2l+1) at doubles
+// [l*RP, l*RP + 2L), RP = 2L + 4 (the pad staggers the LDS banks of
+// neighbouring pairs); it fills exactly the space of the complex plane.
+template <int L>
+constexpr int real_pair_pitch() {
+  return 2 * L + 4;
+}
+template <int L>
+struct RealPairsIn {  // two real rows packed as one complex line, from LDS
+  const double* r;
+  __device__ cplx operator()(int line, int k) const {
+    const double* r0 = r + line * real_pair_pitch<L>();
+    return cplx{r0[k], r0[L + k]};
+  }
+};
+template <int L>
+struct RealPairsOut {  // the inverse: line -> rows 2l, 2l+1 in LDS (in place, so a barrier first)
+  double* r;
+  double scale;
+  __device__ void operator()(int line, int k, cplx v) const {
+    double* r0 = r + line * real_pair_pitch<L>();
+    r0[k] = v.x * scale;
+    r0[L + k] = v.y * scale;
+  }
+  __device__ void barrier_before() const { __syncthreads(); }
+  __device__ void barrier_after() const { __syncthreads(); }
+};
+// LDS double index of plane element q = y*L + z (the global row-major order)
+template <int L>
+__device__ inline int real_at(int q) {
+  const int y = q / L, z = q - (q / L) * L;
+  return (y >> 1) * real_pair_pitch<L>() + (y & 1) * L + z;
+}
+
+// R2C: the real plane is read once with coalesced 16-byte loads (input transform
+// FIN as in the z pass applied on the way) into LDS; z transform of its L/2 row
+// pairs, Hermitian split into the [k_y][k_z] plane, y transform, store.
 template <int L, int FIN, int NT>
 __device__ inline void zy_r2c_body(const ZArgs& A, unsigned bid, cplx* plane, cplx* tw) {
   constexpr int Nh = L / 2 + 1;
   constexpr int NP = L / 2;
   static_assert(NP * (L + 1) <= plane_elems<L>(), "packed rows fit the plane");
+  static_assert(NP * real_pair_pitch<L>() <= 2 * plane_elems<L>(), "real rows fit the plane");
+  static_assert(L % 2 == 0, "pairs of doubles");
   for (int i = threadIdx.x; i < L; i += NT) tw[i] = A.tw[i];
-  __syncthreads();
   const int64_t off = (int64_t)bid * L * L;
-  const double* in = (const double*)A.in + off;
+  const double2* in2 = (const double2*)((const double*)A.in + off);
+  double* rl = (double*)plane;
+  constexpr int N2 = L * L / 2;
+  for (int q = threadIdx.x; q < N2; q += NT) {
+    double2 v = in2[q];
+    if constexpr (FIN == 1) {
+      v.x = sqrt(v.x);
+      v.y = sqrt(v.y);
+    } else if constexpr (FIN == 2) {
+      double2* ni2 = (double2*)(A.f.n_i + off);
+      const double2 b = ni2[q];
+      const double w = *A.f.w;
+      v.x = v.x + w * (b.x - v.x);
+      v.y = v.y + w * (b.y - v.y);
+      ni2[q] = v;
+      v.x = sqrt(v.x);
+      v.y = sqrt(v.y);
+    }
+    const int at = real_at<L>(2 * q);  // 2q and 2q+1 share a row (L even)
+    rl[at] = v.x * A.in_scale;
+    rl[at + 1] = v.y * A.in_scale;
+  }
+  __syncthreads();
   LdsIO<L, NP, false> packed{plane};
-  if constexpr (FIN == 0)
-    run<L, NP, NT, false, -1, 1>(PairIn{in, L, NP, A.in_scale}, packed, plane, tw, NP, typename Plan<L>::R{});
-  else if constexpr (FIN == 1)
-    run<L, NP, NT, false, -1, 1>(PairInSqrt{in, L, NP, A.in_scale}, packed, plane, tw, NP, typename Plan<L>::R{});
-  else
-    run<L, NP, NT, false, -1, 1>(PairInMix{in, A.f.n_i + off, L, NP, A.in_scale, *A.f.w}, packed, plane, tw, NP,
-                                 typename Plan<L>::R{});
+  run<L, NP, NT, false, -1, 1>(RealPairsIn<L>{rl}, packed, plane, tw, NP, typename Plan<L>::R{});
   // split pair l into rows 2l, 2l+1 (read everything, then overwrite in place)
   constexpr int NOUT = L * Nh;
   constexpr int PER = (NOUT + NT - 1) / NT;
@@ -359,8 +411,9 @@ __device__ inline void zy_r2c_body(const ZArgs& A, unsigned bid, cplx* plane, cp
                               plane, tw, Nh, typename Plan<L>::R{});
 }
 
-// C2R: y transform of the plane into LDS, then the z transform of its row pairs
-// (output transform FOUT as in the z pass).
+// C2R: y transform of the plane into LDS, z transform of its row pairs into the
+// real plane in LDS, then one coalesced pass that stores it (or, FOUT = 1,
+// forms the U_vW partial sum of the z pass instead).
 template <int L, int FOUT, int NT>
 __device__ inline void yz_c2r_body(const ZArgs& A, unsigned bid, cplx* plane, cplx* tw, double* sh) {
   constexpr int Nh = L / 2 + 1;
@@ -370,16 +423,30 @@ __device__ inline void yz_c2r_body(const ZArgs& A, unsigned bid, cplx* plane, cp
   const cplx* in = (const cplx*)A.in + (int64_t)bid * L * Nh;
   LdsIO<L, Nh, true> pl{plane};
   run<L, Nh, NT, true, +1, 1>(ColIn{in, Nh, Nh}, pl, plane, tw, Nh, typename Plan<L>::R{});
+  double* rl = (double*)plane;
+  run<L, NP, NT, false, +1, 1>(HermIn{plane, L, Nh, NP}, RealPairsOut<L>{rl, A.out_scale}, plane, tw, NP,
+                               typename Plan<L>::R{});
   const int64_t off = (int64_t)bid * L * L;
+  constexpr int N2 = L * L / 2;
   if constexpr (FOUT == 0) {
-    run<L, NP, NT, false, +1, 1>(HermIn{plane, L, Nh, NP}, PairOut{(double*)A.out + off, L, NP, A.out_scale}, plane,
-                                 tw, NP, typename Plan<L>::R{});
+    double2* out2 = (double2*)((double*)A.out + off);
+    for (int q = threadIdx.x; q < N2; q += NT) {
+      const int at = real_at<L>(2 * q);
+      out2[q] = double2{rl[at], rl[at + 1]};
+    }
   } else {
+    // (v_vW[n_i] - v_vW[n_a]) (n_i - n_a) with v_vW[n] = -(lambda/2) lap / sqrt(n)
+    const double2* ni2 = (const double2*)(A.f.n_i + off);
+    const double2* li2 = (const double2*)(A.f.lap_i + off);
+    const double2* na2 = (const double2*)(A.f.n_a + off);
+    const double hl = 0.5 * A.f.lam;
     double acc = 0.0;
-    run<L, NP, NT, false, +1, 1>(
-        HermIn{plane, L, Nh, NP},
-        PairOutUvw{A.f.n_i + off, A.f.lap_i + off, A.f.n_a + off, L, NP, A.out_scale, 0.5 * A.f.lam, &acc}, plane, tw,
-        NP, typename Plan<L>::R{});
+    for (int q = threadIdx.x; q < N2; q += NT) {
+      const int at = real_at<L>(2 * q);
+      const double2 a = ni2[q], li = li2[q], b = na2[q];
+      acc += (-hl * li.x / sqrt(a.x) + hl * rl[at] / sqrt(b.x)) * (a.x - b.x);
+      acc += (-hl * li.y / sqrt(a.y) + hl * rl[at + 1] / sqrt(b.y)) * (a.y - b.y);
+    }
     acc = block_sum(acc, sh);
     if (threadIdx.x == 0) A.f.partials[bid] = acc;
   }
