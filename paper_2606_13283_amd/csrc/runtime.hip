@@ -169,6 +169,11 @@ arche_status run_scf(arche_ctx* c, arche_result* out) {
       return hip_err(c, e, "scf iteration");
     }
   }
+  // stopped by the iteration cap: the last iteration's state is still to be kept
+  if (!stop && t >= 1) {
+    hipError_t e = hipEventSynchronize(ev[(t - 1) & 1]);
+    if (e == hipSuccess) c->hist.push_back(ring[(t - 1) & 1]);
+  }
   (void)hipEventDestroy(ev[0]);
   (void)hipEventDestroy(ev[1]);
   return collect_state(c, out);

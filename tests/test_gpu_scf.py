@@ -244,3 +244,36 @@ def test_rand1024_sampled():
     rfp, mu = fixed_point_residual(s, ion, n)
     assert rfp <= 100 * 1e-10, rfp
     ctx.close()
+
+
+def test_plane_grid_iteration_parity():
+    """Iteration-by-iteration parity on a grid with N_y = N_z = 128, the shape on
+    which the SCF iteration runs the plane FFT passes (z and y in one pass, with
+    the square root, the mixing and the U_vW sums fused into them) and the paired
+    launches: 128 atoms in a 16 x 128 x 128 slab (0.3-0.4 bohr spacing), seven
+    iterations from the uniform density with More's weight on from the third
+    (trust bound lifted, so U_H, U_xc, U_vW and K all enter), against the
+    oracle's SCF loop (Sec. 2.5, 2.5.2): every residual and every weight."""
+    w = W.small_random(128, 64, 2.7, 10.0, seed=21, shape=(16, 128, 128), stretch=(0.2, 2.2361, 2.2361))
+    say("plane-grid iterations", w.name)
+    its = 7
+    ctx = arche.Context.from_workload(w, opts_of(w, init=arche.INIT_UNIFORM, scf_tol=1e-300, scf_max_iter=its,
+                                                 more_warmup=2, more_trust=1e30))
+    ctx.solve(w.pos, allow_noconv=True)
+    h = ctx.history()
+    ctx.close()
+    assert h.shape[0] == its
+    s = system_of(w)
+    ion = oscf.ionic_setup(s)
+    n0 = np.full(s.shape, s.Ne / s.grid.volume)
+    say("oracle iterations")
+    r = oscf.scf(s, ion, n0, mixing="more", tol=1e-300, max_iter=its, warmup=2, w_fixed=w.w_fixed, more_trust=1e30)
+    say("residuals gpu", h[:, 1], "oracle", r.history)
+    say("weights gpu", h[:, 2], "oracle", r.weights)
+    for t in range(its):
+        assert abs(h[t, 1] - r.history[t]) <= 1e-9 * r.history[t], (t, h[t, 1], r.history[t])
+    # the last iteration raises done before its weight is formed on the GPU
+    for t in range(its - 1):
+        assert abs(h[t, 2] - r.weights[t]) <= 1e-9, (t, h[t, 2], r.weights[t])
+    # More's own weight (not a clamp) was taken in some iterations
+    assert any(abs(x - round(x / 0.05) * 0.05) > 1e-6 for x in r.weights[2:its - 1])
