@@ -84,10 +84,15 @@ arche_status arche_profile_read(arche_ctx *ctx, int32_t kind, double *total_ms, 
 /* Convergence history of the last arche_scf_solve / arche_md_step solve on ctx
  * (empty after batched solves): *n_rows iterations, each row of 10 doubles
  * [iteration, residual, mixing weight w, mu, K, U = U_H + U_xc + U_vW,
- *  max |n_i - n_a| / n_a, Newton passes, More weight on, error flag];
- * the last row may be missing when the solve stopped on the first poll.
- * rows_host may be NULL to query the count. */
+ *  max |n_i - n_a| / n_a, Newton passes, More weight on, error flag], one
+ * row per iteration.  rows_host may be NULL to query the count. */
 arche_status arche_debug_history(arche_ctx *ctx, double *rows_host, int32_t max_rows, int32_t *n_rows);
+
+/* Contexts alive in the process (arche_scf_init .. arche_scf_free, batch members
+ * included).  While it is 1 the SCF kernel runs as a plain launch of its
+ * occupancy-sized grid; otherwise as a cooperative launch (both compute the same
+ * bits). */
+int32_t arche_debug_live_contexts(void);
 
 /* FFT tile variant in use for line length L in pass 0 (y), 1 (x) or 2 (z):
  * 0 = 16 columns (strided) / 32 or 16 row pairs (z) per 256-thread block,

@@ -152,6 +152,8 @@ def load(path: str = LIB_PATH):
     L.arche_set_init_net.restype = st
     L.arche_debug_history.argtypes = [vp, _dp, ctypes.c_int32, _ip]
     L.arche_debug_history.restype = st
+    L.arche_debug_live_contexts.argtypes = []
+    L.arche_debug_live_contexts.restype = ctypes.c_int32
     L.arche_fft_tile.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     L.arche_fft_tile.restype = ctypes.c_int32
     L.arche_k_fft_r2c.argtypes = [_ip, vp, vp, vp]

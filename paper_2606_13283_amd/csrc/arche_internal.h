@@ -2,6 +2,8 @@
 // scalars, and the kernel launchers shared by the translation units.
 #pragma once
 
+#include <atomic>
+
 #include <string>
 #include <vector>
 
@@ -98,6 +100,7 @@ struct MixWeightArgs {
   int nbv;
   int use_vw;
   double vol, dv, w_fixed;
+  ScfState* ring;  // pinned host ring [2]: the state after iteration t goes to ring[t & 1] (null: none)
 };
 struct RealMixArgs {
   const ScfState* st;
@@ -187,6 +190,8 @@ hipError_t finish_sums(const double* partials, int nblk, int nsum, double* out, 
 
 // SCF (scf.hip)
 hipError_t scf_iteration(arche_ctx* c);
+// contexts alive in the process (arche_scf_init .. arche_scf_free, batch members included)
+extern std::atomic<int> g_live_contexts;
 hipError_t scf_reset_state(arche_ctx* c, double mu0);
 hipError_t scf_vw_laplacian(arche_ctx* c, const double* n, double* lap);  // lap = del^2 sqrt(n)
 hipError_t scf_energies(arche_ctx* c, double* out16);  // see scf.hip for the order

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <atomic>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -10,6 +11,8 @@
 
 #include "../../include/arche_kernels.h"
 #include "arche_internal.h"
+
+std::atomic<int> g_live_contexts{0};
 
 namespace {
 
@@ -153,8 +156,8 @@ arche_status run_scf(arche_ctx* c, arche_result* out) {
   bool stop = false;
   int t = 0;
   for (; t < c->p.scf_max_iter && !stop; ++t) {
+    // the iteration's weight kernel writes its state to ring[t & 1] (pinned)
     hipError_t e = scf_iteration(c);
-    if (e == hipSuccess) e = hipMemcpyAsync(&ring[t & 1], c->state, sizeof(ScfState), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipEventRecord(ev[t & 1], c->stream);
     if (e == hipSuccess && t >= 1) {
       e = hipEventSynchronize(ev[(t - 1) & 1]);
@@ -443,6 +446,7 @@ arche_status arche_scf_init(const arche_params* p, void* hip_stream, arche_ctx**
   if (!up) return fail_init(ARCHE_EHIP, "upload failed");
   if (ionic_shells(c) != hipSuccess) return fail_init(ARCHE_ENOMEM, "shell table allocation failed");
   if (fft_tune(&c->plan, c->ctmp, c->rtmp, c->stream) != hipSuccess) return fail_init(ARCHE_EHIP, "FFT tile tuning failed");
+  g_live_contexts.fetch_add(1);
   *out = c;
   return ARCHE_OK;
 }
@@ -562,6 +566,7 @@ void arche_scf_free(arche_ctx* c) {
   free_all(c);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
+  g_live_contexts.fetch_sub(1);
 }
 
 const char* arche_last_error(const arche_ctx* c) { return c ? c->err.c_str() : g_init_err.c_str(); }
@@ -612,6 +617,8 @@ arche_status arche_debug_one_center2(arche_ctx* c, const double* pos_host, doubl
   c->converged = false;
   return ARCHE_OK;
 }
+
+int32_t arche_debug_live_contexts(void) { return g_live_contexts.load(); }
 
 arche_status arche_debug_history(arche_ctx* c, double* rows_host, int32_t max_rows, int32_t* n_rows) {
   if (!c || !n_rows) return ARCHE_EINVAL;

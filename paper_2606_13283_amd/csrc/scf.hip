@@ -470,12 +470,27 @@ k_uh_partial(const ScfState* st, const cplx* nhat_i, const cplx* nhat_a, GridInf
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
+// The state after this iteration into the host's pinned ring: 8-byte words with
+// system-scope stores, so the host sees them once the iteration's event is done.
+__device__ inline void state_to_ring(const MixWeightArgs& m) {
+  static_assert(sizeof(ScfState) % 8 == 0, "whole words");
+  const ScfState* st = m.st;
+  const uint64_t* src = (const uint64_t*)st;
+  uint64_t* dst = (uint64_t*)(m.ring + ((st->iter - 1) & 1));
+  for (int k = 0; k < (int)(sizeof(ScfState) / 8); ++k)
+    __hip_atomic_store(dst + k, src[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // Mixing weight (Sec. 2.5.2): w = U/(U+K) with U = U_H + U_xc + U_vW once the More
 // weight is on, else w_fixed; clamped to [0, 0.995] and to at most W_MAX_DROP
 // below the previous weight.  One block per system.
 __device__ inline void mix_weight_body(const MixWeightArgs& m, double* sh) {
   ScfState* st = m.st;
-  if (st->done) return;
+  if (st->done) {
+    // a converged (or failed) state still reaches the host's ring
+    if (threadIdx.x == 0 && m.ring) state_to_ring(m);
+    return;
+  }
   double a = 0.0, b = 0.0;
   for (int t = threadIdx.x; t < m.nbh; t += blockDim.x) a += m.part_h[t];
   a = block_sum(a, sh);
@@ -495,6 +510,7 @@ __device__ inline void mix_weight_body(const MixWeightArgs& m, double* sh) {
       if (!(w == w)) w = m.w_fixed;
     }
     st->w = w;
+    if (m.ring) state_to_ring(m);
   }
 }
 __global__ void __launch_bounds__(ARCHE_BLOCK) k_mix_weight(MixWeightArgs m) {
@@ -891,7 +907,7 @@ void scf_build_iteration(arche_ctx* c) {
   w.slot = SLOT_WEIGHT;
   w.kind = STEP_WEIGHT;
   w.nblocks = 1;
-  w.mw = MixWeightArgs{c->state, part_h, nbh, part_v, nbv, (int)(more && vw), g.vol, g.dv, p.w_fixed};
+  w.mw = MixWeightArgs{c->state, part_h, nbh, part_v, nbv, (int)(more && vw), g.vol, g.dv, p.w_fixed, c->state_host};
   c->steps.push_back(w);
   if (pair && vw) {
     FftPass pe[3], pf[3];
@@ -960,7 +976,8 @@ static hipError_t scf_iteration_rest_plain(arche_ctx* c) {
   hipLaunchKernelGGL(k_uh_partial, dim3(nbh), dim3(ARCHE_BLOCK), 0, c->stream, (const ScfState*)c->state, c->nhat_i,
                      c->nhat_a, g, part_h);
   HIP_TRY(hipGetLastError());
-  const MixWeightArgs mw{c->state, part_h, nbh, part_v, nbr, (int)(more && vw), g.vol, g.dv, p.w_fixed};
+  const MixWeightArgs mw{c->state, part_h, nbh, part_v, nbr, (int)(more && vw), g.vol, g.dv, p.w_fixed,
+                         c->state_host};
   hipLaunchKernelGGL(k_mix_weight, dim3(1), dim3(ARCHE_BLOCK), 0, c->stream, mw);
   HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_spec_mix, dim3(grid_for(g.nh)), dim3(ARCHE_BLOCK), 0, c->stream, (const ScfState*)c->state,
@@ -985,8 +1002,25 @@ hipError_t scf_iteration(arche_ctx* c) {
   const bool cache = c->active.nchunk <= c->coop_blocks;
   {
     ProfScope prof(PROF_SCF_ACTIVE, c->stream);
-    HIP_TRY(hipLaunchCooperativeKernel(cache ? (const void*)k_scf_active<true> : (const void*)k_scf_active<false>,
-                                       dim3(c->coop_blocks), dim3(ARCHE_BLOCK), args, 0, c->stream));
+    // The kernel's all-reduces need every block resident at once.  The grid is
+    // the occupancy-sized count of one kernel alone on the device; with this
+    // context the only one in the process, nothing else can hold CUs while
+    // waiting on it (other kernels finish by themselves, then the rest of the
+    // grid is dispatched), and a plain launch saves the ~20 us a cooperative
+    // launch spends around the kernel.  With other contexts alive (another
+    // all-reduce kernel could take part of the CUs) the launch is cooperative,
+    // which guarantees residency.  Waits are bounded in any case (a time-out
+    // raises the error flag instead of hanging).
+    if (g_live_contexts.load() == 1) {
+      if (cache)
+        hipLaunchKernelGGL(k_scf_active<true>, dim3(c->coop_blocks), dim3(ARCHE_BLOCK), 0, c->stream, c->active);
+      else
+        hipLaunchKernelGGL(k_scf_active<false>, dim3(c->coop_blocks), dim3(ARCHE_BLOCK), 0, c->stream, c->active);
+      HIP_TRY(hipGetLastError());
+    } else {
+      HIP_TRY(hipLaunchCooperativeKernel(cache ? (const void*)k_scf_active<true> : (const void*)k_scf_active<false>,
+                                         dim3(c->coop_blocks), dim3(ARCHE_BLOCK), args, 0, c->stream));
+    }
   }
   if (!c->fused) return scf_iteration_rest_plain(c);
   for (const IterStep& st : c->steps) HIP_TRY(scf_step_launch(st, c->stream));

@@ -277,3 +277,27 @@ def test_plane_grid_iteration_parity():
         assert abs(h[t, 2] - r.weights[t]) <= 1e-9, (t, h[t, 2], r.weights[t])
     # More's own weight (not a clamp) was taken in some iterations
     assert any(abs(x - round(x / 0.05) * 0.05) > 1e-6 for x in r.weights[2:its - 1])
+
+
+def test_plain_and_cooperative_launch_agree():
+    """The SCF kernel runs as a plain launch while its context is the only one
+    alive and as a cooperative launch otherwise; the arithmetic is the same, so
+    the two solves are bit-identical (density, F, iterations)."""
+    import gc
+    gc.collect()
+    L = arche.load()
+    w = W.small_random(8, 20, 2.7, 5.0, seed=12)
+    ctx = arche.Context.from_workload(w, opts_of(w, init=arche.INIT_UNIFORM))
+    assert L.arche_debug_live_contexts() == 1, "another context is still alive"
+    r1 = ctx.solve(w.pos)
+    n1 = ctx.density()
+    other = arche.Context.from_workload(w, opts_of(w, init=arche.INIT_UNIFORM))
+    assert L.arche_debug_live_contexts() == 2
+    r2 = ctx.solve(w.pos)
+    n2 = ctx.density()
+    other.close()
+    ctx.close()
+    assert r1["converged"] and r2["converged"]
+    assert r1["scf_iters"] == r2["scf_iters"]
+    assert r1["F"] == r2["F"] and r1["mu"] == r2["mu"]
+    assert np.array_equal(n1, n2)
