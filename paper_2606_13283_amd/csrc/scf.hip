@@ -472,55 +472,62 @@ k_uh_partial(const ScfState* st, const cplx* nhat_i, const cplx* nhat_a, GridInf
 
 // The state after this iteration into the host's pinned ring: 8-byte words with
 // system-scope stores, so the host sees them once the iteration's event is done.
-__device__ inline void state_to_ring(const MixWeightArgs& m) {
-  static_assert(sizeof(ScfState) % 8 == 0, "whole words");
-  const ScfState* st = m.st;
-  const uint64_t* src = (const uint64_t*)st;
-  uint64_t* dst = (uint64_t*)(m.ring + ((st->iter - 1) & 1));
-  for (int k = 0; k < (int)(sizeof(ScfState) / 8); ++k)
-    __hip_atomic_store(dst + k, src[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+// The state after this iteration into the host's pinned ring, one 8-byte word
+// per thread with system-scope stores (the host reads it once the iteration's
+// event is done).  `copy` is the block's LDS copy of the state; every thread of
+// the block calls this.
+constexpr int STATE_WORDS = (int)(sizeof(ScfState) / 8);
+static_assert(sizeof(ScfState) % 8 == 0 && STATE_WORDS <= ARCHE_BLOCK, "whole words, one per thread");
+__device__ inline void state_to_ring(const MixWeightArgs& m, ScfState* copy) {
+  if (threadIdx.x == 0) *copy = *m.st;
+  __syncthreads();
+  const int k = threadIdx.x;
+  if (k < STATE_WORDS) {
+    uint64_t* dst = (uint64_t*)(m.ring + ((copy->iter - 1) & 1));
+    __hip_atomic_store(dst + k, ((const uint64_t*)copy)[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
 }
 
 // Mixing weight (Sec. 2.5.2): w = U/(U+K) with U = U_H + U_xc + U_vW once the More
 // weight is on, else w_fixed; clamped to [0, 0.995] and to at most W_MAX_DROP
-// below the previous weight.  One block per system.
-__device__ inline void mix_weight_body(const MixWeightArgs& m, double* sh) {
+// below the previous weight.  One block per system.  A converged (or failed)
+// state skips the weight but still reaches the host's ring.
+__device__ inline void mix_weight_body(const MixWeightArgs& m, double* sh, ScfState* copy) {
   ScfState* st = m.st;
-  if (st->done) {
-    // a converged (or failed) state still reaches the host's ring
-    if (threadIdx.x == 0 && m.ring) state_to_ring(m);
-    return;
-  }
-  double a = 0.0, b = 0.0;
-  for (int t = threadIdx.x; t < m.nbh; t += blockDim.x) a += m.part_h[t];
-  a = block_sum(a, sh);
-  if (m.use_vw && st->more_on)
-    for (int t = threadIdx.x; t < m.nbv; t += blockDim.x) b += m.part_v[t];
-  b = block_sum(b, sh);
-  if (threadIdx.x == 0) {
-    st->UH = a / m.vol;
-    st->Uvw = (m.use_vw && st->more_on) ? m.dv * b : 0.0;
-    double w = m.w_fixed;
-    if (st->more_on) {
-      const double U = st->UH + st->Uxc + st->Uvw;
-      w = U / (U + st->K);
-      w = fmin(fmax(w, 0.0), 0.995);
-      // at most W_MAX_DROP below the previous weight (st->w)
-      w = fmax(w, st->w - W_MAX_DROP);
-      if (!(w == w)) w = m.w_fixed;
+  if (!st->done) {
+    double a = 0.0, b = 0.0;
+    for (int t = threadIdx.x; t < m.nbh; t += blockDim.x) a += m.part_h[t];
+    a = block_sum(a, sh);
+    if (m.use_vw && st->more_on)
+      for (int t = threadIdx.x; t < m.nbv; t += blockDim.x) b += m.part_v[t];
+    b = block_sum(b, sh);
+    if (threadIdx.x == 0) {
+      st->UH = a / m.vol;
+      st->Uvw = (m.use_vw && st->more_on) ? m.dv * b : 0.0;
+      double w = m.w_fixed;
+      if (st->more_on) {
+        const double U = st->UH + st->Uxc + st->Uvw;
+        w = U / (U + st->K);
+        w = fmin(fmax(w, 0.0), 0.995);
+        // at most W_MAX_DROP below the previous weight (st->w)
+        w = fmax(w, st->w - W_MAX_DROP);
+        if (!(w == w)) w = m.w_fixed;
+      }
+      st->w = w;
     }
-    st->w = w;
-    if (m.ring) state_to_ring(m);
   }
+  if (m.ring) state_to_ring(m, copy);
 }
 __global__ void __launch_bounds__(ARCHE_BLOCK) k_mix_weight(MixWeightArgs m) {
   __shared__ double sh[ARCHE_BLOCK / 64];
-  mix_weight_body(m, sh);
+  __shared__ ScfState copy;
+  mix_weight_body(m, sh, &copy);
 }
 __global__ void __launch_bounds__(ARCHE_BLOCK) k_mix_weight_batch(const MixWeightArgs* __restrict__ jobs) {
   __shared__ double sh[ARCHE_BLOCK / 64];
+  __shared__ ScfState copy;
   const MixWeightArgs m = jobs[blockIdx.x];
-  mix_weight_body(m, sh);
+  mix_weight_body(m, sh, &copy);
 }
 
 // n^_o = n^_a + w (n^_i - n^_a) -> nhat_i;  tmp = n^_o / (pi k^2) (0 at k = 0)
