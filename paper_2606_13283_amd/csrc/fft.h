@@ -148,6 +148,9 @@ hipError_t fft_batch_launch(int kind, int sign, int mode, const FftPass* jobs, c
                             unsigned nblocks, hipStream_t s);
 
 bool fft_fusable(const FftPlan* p);
+// x passes of line length L have the MODE 4 round trip (forward, Laplacian,
+// inverse in one pass)
+bool fft_x_roundtrip(int L);
 // N_y = N_z with a plane kernel for that length (the plane fits in LDS)
 bool fft_plane_fusable(const FftPlan* p);
 // number of blocks (= partial sums) of the fused x pass and of the fused z pass

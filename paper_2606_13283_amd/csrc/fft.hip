@@ -391,6 +391,11 @@ constexpr int z_rows_var(int v) {
 }
 constexpr int kZNT[3] = {ARCHE_BLOCK, 128, 64};
 
+// line lengths with plane passes (and the x round trip of MODE 4)
+template <int L>
+constexpr bool plane_len() {
+  return L == 128;
+}
 template <int L, int TK, int NT>
 hipError_t launch_strided_tile(const FftPass& ps, hipStream_t s) {
   const dim3 grid(ps.nblocks), blk(NT);
@@ -398,7 +403,9 @@ hipError_t launch_strided_tile(const FftPass& ps, hipStream_t s) {
   else if (ps.mode == 0) hipLaunchKernelGGL((k_strided_ct<L, TK, +1, 0, NT>), grid, blk, 0, s, ps.s);
   else if (ps.mode == 1) hipLaunchKernelGGL((k_strided_ct<L, TK, -1, 1, NT>), grid, blk, 0, s, ps.s);
   else if (ps.mode == 2) hipLaunchKernelGGL((k_strided_ct<L, TK, -1, 2, NT>), grid, blk, 0, s, ps.s);
-  else hipLaunchKernelGGL((k_strided_ct<L, TK, +1, 3, NT>), grid, blk, 0, s, ps.s);
+  else if (ps.mode == 3) hipLaunchKernelGGL((k_strided_ct<L, TK, +1, 3, NT>), grid, blk, 0, s, ps.s);
+  else if constexpr (plane_len<L>()) hipLaunchKernelGGL((k_strided_ct<L, TK, -1, 4, NT>), grid, blk, 0, s, ps.s);
+  else return hipErrorNotSupported;
   return hipGetLastError();
 }
 template <int L, int B, int NT>
@@ -469,6 +476,10 @@ bool launch_dual_L(const FftPass& a, const FftPass& b, hipStream_t s, hipError_t
   } else if (a.kind == FFT_PASS_STRIDED && b.kind == FFT_PASS_STRIDED && a.var == 0 && b.var == 0 && a.sign < 0 &&
              b.sign < 0 && a.mode == 2 && b.mode == 1) {
     hipLaunchKernelGGL((k_strided_dual<L, kStridedTK[0], -1, 2, -1, 1, kStridedNT[0]>), dim3(a.nblocks + b.nblocks),
+                       dim3(kStridedNT[0]), 0, s, a.s, b.s, a.nblocks);
+  } else if (a.kind == FFT_PASS_STRIDED && b.kind == FFT_PASS_STRIDED && a.var == 0 && b.var == 0 && a.sign < 0 &&
+             a.mode == 2 && b.mode == 4) {
+    hipLaunchKernelGGL((k_strided_dual<L, kStridedTK[0], -1, 2, -1, 4, kStridedNT[0]>), dim3(a.nblocks + b.nblocks),
                        dim3(kStridedNT[0]), 0, s, a.s, b.s, a.nblocks);
   } else {
     return false;
@@ -737,6 +748,7 @@ int fft_x_blocks(const FftPlan* p) {
   const int tk = kStridedTK[p->N[0] <= 1024 ? g_tile_var[1][p->N[0]] : 0];
   return p->N[1] * ((p->Nh + tk - 1) / tk);
 }
+bool fft_x_roundtrip(int L) { return L == 128; }  // plane_len
 bool fft_plane_fusable(const FftPlan* p) {
   return fft_fusable(p) && p->N[1] == p->N[2] && plane_supported(p->N[2]);
 }

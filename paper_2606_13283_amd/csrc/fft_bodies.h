@@ -85,8 +85,23 @@ struct ColInMix {  // C2R_IN_MIX: n_o^ = a + w (nhat_i - a); nhat_i <- n_o^; val
   }
 };
 
+struct LdsLap {  // MODE 4: the forward result times -(2 pi |k|)^2 scale, back into LDS
+  cplx* buf;
+  double scale;
+  XGeom g;
+  int o, c0, TK;
+  __device__ void operator()(int line, int k, cplx v) const {
+    const double q2 = 39.478417604357434 * g.k2(k, o, c0 + line);  // (2 pi)^2 |k|^2
+    buf[k * TK + line] = cscale(v, -q2 * scale);
+  }
+  __device__ void barrier_before() const { __syncthreads(); }
+  __device__ void barrier_after() const { __syncthreads(); }
+};
+
 // One tile (block `bid` of the pass).  MODE 0: plain pass.  MODE 1/2/3: x pass
-// with R2C_OUT_LAP / R2C_OUT_UH / C2R_IN_MIX.
+// with R2C_OUT_LAP / R2C_OUT_UH / C2R_IN_MIX.  MODE 4: the x pass of R2C with
+// the Laplacian followed by the x pass of the C2R that comes back from it, in
+// one pass: forward along the line, times -(2 pi |k|)^2 scale, inverse, store.
 template <int L, int TK, int S, int MODE, int NT = ARCHE_BLOCK>
 __device__ inline void strided_body(const StridedArgs& A, unsigned bid, cplx* lds, cplx* tw, double* sh) {
   for (int i = threadIdx.x; i < L; i += NT) tw[i] = A.tw[i];
@@ -109,10 +124,17 @@ __device__ inline void strided_body(const StridedArgs& A, unsigned bid, cplx* ld
         lds, tw, nc, typename Plan<L>::R{});
     acc = block_sum(acc, sh);
     if (threadIdx.x == 0) A.f.partials[bid] = acc;
-  } else {
+  } else if constexpr (MODE == 3) {
     const int64_t off = (int64_t)o * A.os + c0;
     run<L, TK, NT, true, S, 1>(ColInMix{A.src + off, A.f.nhat_i + off, es, nc, *A.f.w, A.g, o, c0},
                                          ColOut{base, es, nc, A.scale}, lds, tw, nc, typename Plan<L>::R{});
+  } else {
+    static_assert(MODE == 4, "modes 0-4");
+    static_assert(nstages(typename Plan<L>::R{}) > 1, "the tile is staged in LDS");
+    run<L, TK, NT, true, -1, 1>(ColIn{base, es, nc}, LdsLap{lds, A.scale, A.g, o, c0, TK}, lds, tw, nc,
+                                typename Plan<L>::R{});
+    run<L, TK, NT, true, +1, 1>(LdsIO<L, TK, true>{lds}, ColOut{base, es, nc, 1.0}, lds, tw, nc,
+                                typename Plan<L>::R{});
   }
 }
 template <int L, int TK>

@@ -890,15 +890,21 @@ void scf_build_iteration(arche_ctx* c) {
   const bool pair = fft_plane_fusable(&c->plan);
   FftPass ps[3];
   fft_r2c_passes(&c->plan, c->n_a, c->nhat_a, 1.0, g.dv, FUSE_NONE, R2C_OUT_UH, f, ps);
+  // Where the x length has it (rt), the Laplacian of sqrt n goes forward along
+  // x, is multiplied, and comes back along x at once (x pass MODE 4), so the C2R
+  // that follows starts at its plane pass.
+  const bool rt = pair && fft_x_roundtrip(g.N[0]);
   if (pair && more && vw) {
     FftPass pb[3];
     fft_r2c_passes(&c->plan, c->n_a, c->ctmp, 1.0, g.dv, R2C_IN_SQRT, R2C_OUT_LAP, f, pb);
+    if (rt) pb[2].mode = 4;
     push_dual(c->steps, SLOT_NHAT_A, ps[0], pb[0]);
     push_dual(c->steps, SLOT_NHAT_A + 2, ps[2], pb[2]);
     FftFuse fv = f;
     fv.partials = part_v;
     fft_c2r_passes(&c->plan, c->ctmp, c->ctmp, nullptr, 1.0 / g.vol, FUSE_NONE, C2R_OUT_UVW, fv, ps);
-    push_fft(c->steps, SLOT_UVW, ps);
+    if (!rt) push_pass(c->steps, SLOT_UVW, ps[0]);
+    push_pass(c->steps, SLOT_UVW + 2, ps[2]);
   } else {
     push_fft(c->steps, SLOT_NHAT_A, ps);
   }
@@ -920,11 +926,13 @@ void scf_build_iteration(arche_ctx* c) {
     FftPass pe[3], pf[3];
     fft_c2r_passes(&c->plan, c->nhat_a, c->ctmp, c->VH, 1.0 / g.vol, C2R_IN_MIX, FUSE_NONE, f, pe);
     fft_r2c_passes(&c->plan, c->n_a, c->ctmp2, 1.0, g.dv, R2C_IN_MIX_SQRT, R2C_OUT_LAP, f, pf);
+    if (rt) pf[2].mode = 4;
     push_pass(c->steps, SLOT_HARTREE, pe[0]);
     push_dual(c->steps, SLOT_HARTREE + 2, pe[2], pf[0]);
     push_pass(c->steps, SLOT_SQRT_O + 2, pf[2]);
     fft_c2r_passes(&c->plan, c->ctmp2, c->ctmp2, c->lap_i, 1.0 / g.vol, FUSE_NONE, FUSE_NONE, f, ps);
-    push_fft(c->steps, SLOT_LAP_O, ps);
+    if (!rt) push_pass(c->steps, SLOT_LAP_O, ps[0]);
+    push_pass(c->steps, SLOT_LAP_O + 2, ps[2]);
     return;
   }
   fft_c2r_passes(&c->plan, c->nhat_a, c->ctmp, c->VH, 1.0 / g.vol, C2R_IN_MIX, FUSE_NONE, f, ps);
