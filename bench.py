@@ -115,12 +115,19 @@ def bench_batch(count):
         return arche.Options(w_fixed=w.w_fixed, lambda_vw=w.lam, xc=arche.XC_LDA if w.xc else arche.XC_NONE,
                              init=arche.INIT_UNIFORM, scf_tol=1e-10)
 
-    ctxs = [arche.Context.from_workload(w, opts(w)) for w in ws]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    seq = [c.solve(w.pos) for c, w in zip(ctxs, ws)]
-    t_seq = time.perf_counter() - t0
-    for c in ctxs:
+    # one after another, each on its own context with no other context alive (the
+    # single-system path at its fastest: plain launches of the SCF kernel); the
+    # clock covers the solves, not the contexts' creation
+    seq = []
+    t_seq = 0.0
+    for w in ws:
+        o = opts(w)
+        o.exclusive_device = 1
+        c = arche.Context.from_workload(w, o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        seq.append(c.solve(w.pos))
+        t_seq += time.perf_counter() - t0
         c.close()
     print("[bench] batch: %d sequential solves in %.3f s (%d SCF iterations)" % (
         len(ws), t_seq, sum(r["scf_iters"] for r in seq)), file=sys.stderr, flush=True)
@@ -246,7 +253,8 @@ def main():
     arche.load()
     w = getattr(W, args.workload)()
     stream = torch.cuda.current_stream().cuda_stream
-    opts = arche.Options(w_fixed=w.w_fixed, init=arche.INIT_ONE_CENTER, scf_tol=1e-10)
+    # the benchmark owns the GPU: the SCF kernel may be a plain launch
+    opts = arche.Options(w_fixed=w.w_fixed, init=arche.INIT_ONE_CENTER, scf_tol=1e-10, exclusive_device=1)
     ctx = arche.Context.from_workload(w, opts, stream=stream)
     pos = w.pos.copy()
     vel = w.vel.copy() if w.vel is not None else np.zeros_like(pos)
@@ -262,9 +270,12 @@ def main():
     first_s = time.perf_counter() - t0
     print("[bench] first solve: %d SCF iterations in %.3f s" % (first["scf_iters"], first_s), file=sys.stderr,
           flush=True)
+    F_prev = first["F"]
     for k in range(args.warmup):
         pos, vel, F, res = ctx.md_step(dt, pos, vel)
+        F_prev = res["F"]
         print("[bench] warmup step %d: %d SCF iterations" % (k, res["scf_iters"]), file=sys.stderr, flush=True)
+    mass = np.array([w.mass[s] for s in w.species])[:, None]
 
     # the timed steps time the SCF kernel alone (every timed launch adds an
     # event pair and a gap before the next launch)
@@ -276,12 +287,19 @@ def main():
     ev0.record()
     t0 = time.perf_counter()
     iters = newton = 0
-    per_step = []
+    per_step, fallback, Ki, conserved = [], [], [], []
     for k in range(args.steps):
         pos, vel, F, res = ctx.md_step(dt, pos, vel)
         iters += res["scf_iters"]
         newton += res["newton_iters"]
         per_step.append(res["scf_iters"])
+        fallback.append(int(res["used_fallback"]))
+        # the step returns v(t) (central difference) and F at t + dt: pair v(t) with
+        # the previous step's free energy F(t) for the conserved K^i + F
+        kin = 0.5 * float(np.sum(mass * vel * vel))
+        Ki.append(kin)
+        conserved.append(kin + F_prev)
+        F_prev = res["F"]
         print("[bench] step %d: %d SCF iterations, F = %.12f Ha, P = %.6e Ha/bohr^3" % (
             k, res["scf_iters"], res["F"], res["P"]), file=sys.stderr, flush=True)
     ev1.record()
@@ -330,6 +348,10 @@ def main():
         "grid_point_updates_per_s": ng * value,
         "event_s": ev_s,
         "scf_iters_each_step": per_step,
+        "used_fallback_each_step": fallback,
+        "ion_kinetic_each_step": Ki,
+        "conserved_Ki_plus_F_each_step": conserved,
+        "conserved_drift_rel": (conserved[-1] - conserved[0]) / abs(conserved[0]) if conserved else None,
         "first_solve": {"scf_iters": first["scf_iters"], "s": first_s},
         "kernels": kernels,
         "kernels_all_classes_one_untimed_step": kernels_step,

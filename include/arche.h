@@ -13,8 +13,9 @@
  *     (i,j,k) sits at (i Lx/Nx, j Ly/Ny, k Lz/Nz) (Sec. 2.3).
  *   - Pointers named *_host are host memory owned by the caller; the library
  *     copies in/out and keeps no reference after the call returns.
- *   - The context owns all device memory it allocates (hipMalloc on the
- *     device current at arche_scf_init) and frees it in arche_scf_free.
+ *   - The context owns all device memory it allocates (on the device current
+ *     at arche_scf_init, through the allocator installed by arche_set_allocator
+ *     at that time, else hipMalloc) and frees it in arche_scf_free.
  *   - Every call returns an arche_status; no call aborts or prints.  After an
  *     error, arche_last_error(ctx) describes it.
  *   - A context is used by one host thread at a time.
@@ -72,6 +73,29 @@ typedef struct {
   double more_trust;        /* ... once max |n_i - n_a| / n_a <= more_trust (e.g. 0.5) */
   double w_fixed;           /* fixed weight w of n_o = n_a + w (n_i - n_a) (e.g. 0.95) */
   int32_t init;             /* ARCHE_INIT_* for arche_scf_solve */
+  /* Optional fields below: zero (e.g. a zero-initialised struct) selects the default. */
+  const double *ff_table;   /* NULL: the analytic empty-core form factor of rc.  Otherwise a
+                               tabulated local pseudopotential (eq. iepseudo takes any radial
+                               V_s(|k|)), [n_species][ff_len] samples of its non-Coulomb part
+                               D_s(q) = V_s(q) + Z_s / (pi q^2) at q = i * ff_dq (q = |k| in
+                               1/bohr, i = 0..ff_len-1).  D_s(0), the limit q -> 0, is the
+                               k = 0 term of E^ie (Sec. 2.6.5).  Between nodes D_s is the cubic
+                               through the nodes i-1, i, i+1, i+2 around q (local cubic
+                               Lagrange, with D_s(-q) = D_s(q) at the first interval), and
+                               dV_s/dq, which enters the pressure, is that cubic's derivative
+                               plus 2 Z_s / (pi q^3).  The table must extend two nodes past
+                               the largest |k| of the grid (EINVAL otherwise).  rc is then
+                               not used.  Copied at init. */
+  int32_t ff_len;           /* nodes per species (>= 4 when ff_table is set) */
+  double ff_dq;             /* node spacing in 1/bohr (> 0 when ff_table is set) */
+  double ewald_alpha;       /* Ewald splitting parameter (1/bohr) of Sec. 2.6.3; <= 0: the
+                               automatic sqrt(pi k_c / r_c), k_c = min N/(2L), r_c = min L/2 */
+  int32_t exclusive_device; /* nonzero: the caller guarantees that nothing else runs on the
+                               device during this context's solves (no other process, no
+                               other live arche context); the SCF kernel, whose grid-wide
+                               reductions need all its blocks resident, is then a plain launch
+                               (~20 us less per iteration than a cooperative one).  0: a
+                               cooperative launch, which guarantees residency. */
 } arche_params;
 
 /* Energy terms (Hartree), index into arche_result.terms */
@@ -151,6 +175,19 @@ arche_status arche_set_density(arche_ctx *ctx, const double *src, int32_t src_on
 arche_status arche_reset_history(arche_ctx *ctx);
 
 void arche_scf_free(arche_ctx *ctx);
+
+/* Device memory of contexts and batches created from now on (Sec. 5.2 keeps
+ * every field resident on the GPU for the whole run; this lets the caller's
+ * memory manager, e.g. PyTorch's caching allocator, supply it).
+ * alloc(bytes, stream) returns device memory on the current device, aligned
+ * to 256 bytes, or NULL on failure (the init call then returns ENOMEM);
+ * release(ptr, stream) gives it back.  `stream` is the context's hipStream_t.
+ * A context keeps the pair it was created with and releases through it in
+ * arche_scf_free, whatever is installed by then.  Both NULL: hipMalloc /
+ * hipFree again.  EINVAL if exactly one is NULL.  Process-wide; not
+ * synchronised with concurrent arche_scf_init calls on other threads. */
+arche_status arche_set_allocator(void *(*alloc)(size_t bytes, void *stream),
+                                 void (*release)(void *ptr, void *stream));
 
 /* Per-context message of the last error (empty if none); valid until the next
  * call on ctx.  With ctx == NULL, the message of the last failed arche_scf_init

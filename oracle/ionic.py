@@ -8,6 +8,12 @@ Ionic field (Sec. 2.4, eq. iepseudo, with V^_s(0) = 0 per Payne):
     V^ie^(k) = sum_s V^_s(k) S_s(k)
 Form factor (empty-core local pseudopotential, fixed by the workload):
     V^_s(k) = -Z_s cos(2 pi |k| r_c) / (pi |k|^2)    [= -4 pi Z cos(G r_c)/G^2]
+  or tabulated (eq. iepseudo takes any radial local pseudopotential): the
+  non-Coulomb part D_s(q) = V^_s(q) + Z_s/(pi q^2), q = |k|, given at the nodes
+  q_i = i dq, and between nodes the cubic through the four nodes i-1, i, i+1,
+  i+2 around q (Lagrange interpolation; D_s is even in q, so node -1 carries
+  the value of node 1).  dV^_s/dq is that cubic's derivative plus
+  2 Z_s/(pi q^3); D_s(0) is the k = 0 limit entering E_alpha.
 Ewald (Sec. 2.6.3): U^ii = U^pp + U^pm + U^je with
     U^pp = sum_{j<l} Z_j Z_l erfc(alpha d)/d         (minimum image)
     U^pm = 1/(2|Omega|) sum_{k != 0} V^_alpha |S_Z|^2 - alpha/sqrt(pi) sum_j Z_j^2
@@ -48,20 +54,70 @@ def structure_factors(g: Grid, pos: np.ndarray, species: np.ndarray, n_species: 
     return S
 
 
-def form_factor(g: Grid, Z: float, rc: float) -> np.ndarray:
+class Tabulated:
+    """A species' tabulated non-Coulomb form factor D(q_i), q_i = i dq (1/bohr)."""
+
+    def __init__(self, table, dq):
+        self.table = np.asarray(table, dtype=np.float64).reshape(-1)
+        self.dq = float(dq)
+
+    def interpolate(self, q):
+        """(D(q), dD/dq) by the local cubic through nodes i-1..i+2, i = floor(q/dq)."""
+        x = np.asarray(q, dtype=np.float64) / self.dq
+        i = np.floor(x).astype(np.int64)
+        t = x - i
+        f = self.table
+        if np.any(i + 2 >= f.size):
+            raise ValueError("form factor table too short for this grid")
+        nodes = [np.where(i == 0, 1, i - 1), i, i + 1, i + 2]  # node -1 mirrors node 1
+        offs = [-1.0, 0.0, 1.0, 2.0]
+        val = np.zeros_like(t)
+        der = np.zeros_like(t)
+        for a in range(4):
+            # Lagrange basis polynomial of node a on the offsets -1, 0, 1, 2
+            num = np.ones_like(t)
+            den = 1.0
+            dnum = np.zeros_like(t)
+            for b in range(4):
+                if b == a:
+                    continue
+                # product rule for the derivative of prod_b (t - o_b)
+                dnum = dnum * (t - offs[b]) + num
+                num = num * (t - offs[b])
+                den *= offs[a] - offs[b]
+            val += f[nodes[a]] * num / den
+            der += f[nodes[a]] * dnum / den
+        return val, der / self.dq
+
+
+def form_factor(g: Grid, Z: float, rc) -> np.ndarray:
+    """V^_s(|k|) on the box, zero at k = 0; rc is the empty-core radius or a Tabulated."""
     V = np.zeros(g.shape)
     q = g.kabs[g.nonzero]
-    V[g.nonzero] = -Z * np.cos(TWO_PI * q * rc) / (math.pi * q * q)
+    if isinstance(rc, Tabulated):
+        V[g.nonzero] = rc.interpolate(q)[0] - Z / (math.pi * q * q)
+    else:
+        V[g.nonzero] = -Z * np.cos(TWO_PI * q * rc) / (math.pi * q * q)
     return V
 
 
-def form_factor_dq(g: Grid, Z: float, rc: float) -> np.ndarray:
+def form_factor_dq(g: Grid, Z: float, rc) -> np.ndarray:
     """dV^_s/d|k| (zero at k = 0, where it is not used)."""
     D = np.zeros(g.shape)
     q = g.kabs[g.nonzero]
+    if isinstance(rc, Tabulated):
+        D[g.nonzero] = rc.interpolate(q)[1] + 2.0 * Z / (math.pi * q ** 3)
+        return D
     a = TWO_PI * q * rc
     D[g.nonzero] = Z * (TWO_PI * rc * np.sin(a) / (q * q) + 2.0 * np.cos(a) / q ** 3) / math.pi
     return D
+
+
+def form_factor_k0(Z: float, rc) -> float:
+    """lim_{k->0} [V^_s(k) + Z/(pi k^2)]: 2 pi Z r_c^2 for the empty core, D(0) for a table."""
+    if isinstance(rc, Tabulated):
+        return float(rc.table[0])
+    return TWO_PI * Z * rc ** 2
 
 
 def ionic_potential_hat(g: Grid, S: np.ndarray, Z, rc) -> np.ndarray:
@@ -91,8 +147,10 @@ def min_image(d: np.ndarray, cell) -> np.ndarray:
     return d - L * np.round(d / L)
 
 
-def ewald(g: Grid, pos, Zj, SZ, alpha=None):
-    """Return dict with U_pp, U_pm, U_je, U_ii and forces F_pp, F_pm (N_i x 3)."""
+def ewald(g: Grid, pos, Zj, SZ, alpha=None, atoms=None):
+    """Return dict with U_pp, U_pm, U_je, U_ii and forces F_pp, F_pm (N_i x 3).
+    With `atoms` given, F_pm is formed only for those atoms (rows of the others
+    stay zero): the reciprocal-space sum per atom is the costly part."""
     if alpha is None:
         alpha = ewald_alpha(g)
     n = pos.shape[0]
@@ -114,7 +172,7 @@ def ewald(g: Grid, pos, Zj, SZ, alpha=None):
     Q = float(np.sum(Zj))
     U_je = -math.pi * Q * Q / (2.0 * alpha ** 2 * g.volume)
     F_pm = np.zeros((n, 3))
-    for j in range(n):
+    for j in (range(n) if atoms is None else atoms):
         kr = g.k[0] * pos[j, 0] + g.k[1] * pos[j, 1] + g.k[2] * pos[j, 2]
         im = np.imag(np.exp(1j * TWO_PI * kr) * SZ) * Va
         for a in range(3):
@@ -147,7 +205,7 @@ def ewald_stress_trace_printed(g: Grid, pos, Zj, SZ, alpha):
 def e_alpha(g: Grid, species, Z, rc) -> float:
     Ne = float(sum(Z[s] for s in species))
     nbar = Ne / g.volume
-    return nbar * float(sum(TWO_PI * Z[s] * rc[s] ** 2 for s in species))
+    return nbar * float(sum(form_factor_k0(Z[s], rc[s]) for s in species))
 
 
 def electron_ion_energy(g: Grid, n, Vie, species, Z, rc) -> float:

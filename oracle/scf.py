@@ -79,12 +79,14 @@ class System:
     kT: float  # Hartree
     lam: float = 0.2  # von Weizsaecker coefficient
     xc: bool = True  # Dirac + PZ81 LDA
+    ewald_alpha: float = 0.0  # Ewald splitting; <= 0: the automatic choice
 
     def __post_init__(self):
         self.pos = np.asarray(self.pos, dtype=np.float64).reshape(-1, 3)
         self.species = np.asarray(self.species, dtype=np.int64).reshape(-1)
         self.Z = tuple(float(z) for z in self.Z)
-        self.rc = tuple(float(r) for r in self.rc)
+        # per species: empty-core radius, or a tabulated form factor (ionic.Tabulated)
+        self.rc = tuple(r if isinstance(r, ionic.Tabulated) else float(r) for r in self.rc)
         self.mass = tuple(float(m) for m in self.mass)
         self.grid = Grid(self.cell, self.shape)
         self.Zj = np.array([self.Z[s] for s in self.species])
@@ -92,7 +94,7 @@ class System:
 
     def with_positions(self, pos):
         return System(self.cell, self.shape, pos, self.species, self.Z, self.rc, self.mass,
-                      self.kT, self.lam, self.xc)
+                      self.kT, self.lam, self.xc, self.ewald_alpha)
 
 
 @dataclass
@@ -276,3 +278,4 @@ def scf(sys: System, ion: Ionic, n_init: np.ndarray, mixing="more", tol=1e-10, m
         ws.append(w)
         n_i = n_a + w * dn
     return SCFResult(n_a, eta, mu, V, max_iter, r, False, hist, newt, ws)
+

@@ -66,7 +66,8 @@ def evaluate(sys: System, ion: Ionic, res: SCFResult, forces=True, atoms=None) -
         F_xc = 0.0
         P_xc = 0.0
     E_ie = ionic.electron_ion_energy(g, n, ion.Vie, sys.species, sys.Z, sys.rc)
-    ew = ionic.ewald(g, sys.pos, sys.Zj, ion.SZ)
+    ew = ionic.ewald(g, sys.pos, sys.Zj, ion.SZ, alpha=sys.ewald_alpha if sys.ewald_alpha > 0 else None,
+                     atoms=atoms if forces else [])
     U_ii = ew["U_ii"]
     F = F_TF + F_vW + E_H + F_xc + E_ie + U_ii
     E = K_e + F_vW + E_H + F_xc + E_ie + U_ii

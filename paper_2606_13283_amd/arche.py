@@ -43,6 +43,8 @@ class Params(ctypes.Structure):
         ("scf_tol", ctypes.c_double), ("scf_max_iter", ctypes.c_int32), ("mixing", ctypes.c_int32),
         ("more_warmup", ctypes.c_int32), ("more_trust", ctypes.c_double), ("w_fixed", ctypes.c_double),
         ("init", ctypes.c_int32),
+        ("ff_table", _dp), ("ff_len", ctypes.c_int32), ("ff_dq", ctypes.c_double),
+        ("ewald_alpha", ctypes.c_double), ("exclusive_device", ctypes.c_int32),
     ]
 
 
@@ -63,6 +65,40 @@ class Result(ctypes.Structure):
 
 
 _lib = None
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+_allocator_keep = None  # the installed callbacks (kept alive while installed)
+
+
+def use_torch_allocator(on: bool = True):
+    """Install (on=True) or remove PyTorch's caching allocator as the source of
+    the device memory of contexts and batches created afterwards
+    (arche_set_allocator).  Memory is requested on the context's stream and
+    returned when the context is freed."""
+    global _allocator_keep
+    import torch
+    L = load()
+    if not on:
+        s = L.arche_set_allocator(_ALLOC_FN(), _RELEASE_FN())
+        if s != OK:
+            raise ArcheError(s, "arche_set_allocator")
+        _allocator_keep = None
+        return
+
+    def alloc(nbytes, stream):
+        try:
+            return int(torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0)))
+        except Exception:
+            return None
+
+    def release(ptr, stream):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    fa, fr = _ALLOC_FN(alloc), _RELEASE_FN(release)
+    s = L.arche_set_allocator(fa, fr)
+    if s != OK:
+        raise ArcheError(s, "arche_set_allocator")
+    _allocator_keep = (fa, fr)
 
 
 def load(path: str = LIB_PATH):
@@ -160,6 +196,8 @@ def load(path: str = LIB_PATH):
     L.arche_k_fft_r2c.restype = st
     L.arche_k_fft_c2r.argtypes = [_ip, vp, vp, vp]
     L.arche_k_fft_c2r.restype = st
+    L.arche_set_allocator.argtypes = [_ALLOC_FN, _RELEASE_FN]
+    L.arche_set_allocator.restype = st
     L.arche_k_fermi_dirac.argtypes = [ctypes.c_int64, vp, vp, vp, vp, vp]
     L.arche_k_fermi_dirac.restype = st
     L.arche_k_fermi_dirac_derivs.argtypes = [ctypes.c_int64, vp, vp, vp, vp, vp, vp]
@@ -190,6 +228,12 @@ class Options:
     init: int = INIT_ONE_CENTER
     lambda_vw: float = 0.2
     xc: int = XC_LDA
+    # tabulated non-Coulomb form factor D_s(q) = V_s(q) + Z_s/(pi q^2) at q = i ff_dq,
+    # shape (n_species, ff_len); None: the analytic empty core of rc
+    ff_table: object = None
+    ff_dq: float = 0.0
+    ewald_alpha: float = 0.0  # <= 0: automatic
+    exclusive_device: int = 0  # 1: nothing else runs on the GPU (plain launch of the SCF kernel)
 
 
 def _make_params(cell, grid, species, Z, rc, mass, kT, opts: Options | None = None):
@@ -215,7 +259,16 @@ def _make_params(cell, grid, species, Z, rc, mass, kT, opts: Options | None = No
     p.more_trust = float(o.more_trust)
     p.w_fixed = float(o.w_fixed)
     p.init = int(o.init)
-    return p, (species, Z, rc, mass)
+    keep = [species, Z, rc, mass]
+    if o.ff_table is not None:
+        ff = np.ascontiguousarray(np.asarray(o.ff_table, dtype=np.float64).reshape(Z.size, -1))
+        keep.append(ff)
+        p.ff_table = _ptr(ff)
+        p.ff_len = ff.shape[1]
+        p.ff_dq = float(o.ff_dq)
+    p.ewald_alpha = float(o.ewald_alpha)
+    p.exclusive_device = int(o.exclusive_device)
+    return p, tuple(keep)
 
 
 class Context:

@@ -49,7 +49,32 @@ struct SpeciesInfo {
   int ns;
   double Z[ARCHE_MAX_SPECIES];
   double rc[ARCHE_MAX_SPECIES];
+  // tabulated form factor (null: analytic empty core): non-Coulomb part
+  // D_s(q) = V_s(q) + Z_s/(pi q^2) at q = i ff_dq, [ns][ff_len], device
+  const double* ff;
+  int ff_len;
+  double ff_dq;
 };
+
+// Device memory of a context: the allocator installed by arche_set_allocator
+// when the context was created (null pair: hipMalloc / hipFree).
+struct DevAllocator {
+  void* (*alloc)(size_t, void*) = nullptr;
+  void (*release)(void*, void*) = nullptr;
+  hipError_t get(void** p, size_t bytes, hipStream_t s) const {
+    if (!alloc) return hipMalloc(p, bytes);
+    *p = alloc(bytes, (void*)s);
+    return *p ? hipSuccess : hipErrorOutOfMemory;
+  }
+  void put(void* p, hipStream_t s) const {
+    if (!p) return;
+    if (release)
+      release(p, (void*)s);
+    else
+      (void)hipFree(p);
+  }
+};
+DevAllocator current_allocator();
 
 // Arguments of the cooperative SCF kernel for one system (scf.hip): steps 1-4
 // of an iteration (potential, chemical potential, active density, sums).
@@ -123,6 +148,9 @@ struct arche_ctx {
   arche_params p;  // copy; pointer members are not kept
   std::vector<int32_t> species;
   std::vector<double> Z, rc, mass;
+  std::vector<double> ff_host;  // tabulated form factor [ns][ff_len] (empty: analytic)
+  double* ff_d = nullptr;
+  DevAllocator dalloc_;         // where this context's device memory comes from
   std::vector<double> Zj;  // per atom
   int n_atoms = 0, n_species = 0;
   double Ne = 0, Q = 0, sumZ2 = 0;

@@ -74,6 +74,7 @@ struct arche_batch {
   ScfState** states_d = nullptr;
   int* done_d = nullptr;
   int* done_h = nullptr;  // pinned [2][n]
+  DevAllocator dalloc_;   // the allocator installed when the batch was created
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   bool graph_full = false;
@@ -193,10 +194,10 @@ arche_status build_tables(arche_batch* b, int budget) {
   BK(hipStreamSynchronize(b->stream));
   drop_graph(b);
   if (t.buf.size() > b->dev_cap) {
-    if (b->dev) (void)hipFree(b->dev);
+    b->dalloc_.put(b->dev, b->stream);
     b->dev = nullptr;
     b->dev_cap = 0;
-    BK(hipMalloc(&b->dev, t.buf.size()));
+    BK(b->dalloc_.get((void**)&b->dev, t.buf.size(), b->stream));
     b->dev_cap = t.buf.size();
   }
   BK(hipMemcpy(b->dev, t.buf.data(), t.buf.size(), hipMemcpyHostToDevice));
@@ -439,6 +440,7 @@ arche_status arche_batch_init(int32_t n_snap, const arche_params* p, void* hip_s
     return s;
   };
   b->n = n_snap;
+  b->dalloc_ = current_allocator();
   for (int i = 0; i < n_snap; ++i)
     for (int a = 0; a < 3; ++a)
       if (!fft_batch_supported(p[i].grid[a])) return fail(ARCHE_EINVAL);
@@ -460,8 +462,9 @@ arche_status arche_batch_init(int32_t n_snap, const arche_params* p, void* hip_s
   if (b->cap < 1) return fail(ARCHE_EHIP);
   std::vector<ScfState*> sts;
   for (arche_ctx* c : b->ctx) sts.push_back(c->state);
-  if (hipMalloc(&b->states_d, n_snap * sizeof(ScfState*)) != hipSuccess) return fail(ARCHE_ENOMEM);
-  if (hipMalloc(&b->done_d, n_snap * sizeof(int)) != hipSuccess) return fail(ARCHE_ENOMEM);
+  if (b->dalloc_.get((void**)&b->states_d, n_snap * sizeof(ScfState*), b->stream) != hipSuccess)
+    return fail(ARCHE_ENOMEM);
+  if (b->dalloc_.get((void**)&b->done_d, n_snap * sizeof(int), b->stream) != hipSuccess) return fail(ARCHE_ENOMEM);
   if (hipHostMalloc((void**)&b->done_h, 2 * n_snap * sizeof(int), hipHostMallocDefault) != hipSuccess)
     return fail(ARCHE_ENOMEM);
   if (hipMemcpy(b->states_d, sts.data(), n_snap * sizeof(ScfState*), hipMemcpyHostToDevice) != hipSuccess)
@@ -530,9 +533,9 @@ void arche_batch_free(arche_batch* b) {
   if (b->stream) (void)hipStreamSynchronize(b->stream);
   drop_graph(b);
   for (arche_ctx* c : b->ctx) arche_scf_free(c);
-  if (b->dev) (void)hipFree(b->dev);
-  if (b->states_d) (void)hipFree(b->states_d);
-  if (b->done_d) (void)hipFree(b->done_d);
+  b->dalloc_.put(b->dev, b->stream);
+  b->dalloc_.put(b->states_d, b->stream);
+  b->dalloc_.put(b->done_d, b->stream);
   if (b->done_h) (void)hipHostFree(b->done_h);
   if (b->own_stream) (void)hipStreamDestroy(b->stream);
   delete b;

@@ -31,6 +31,16 @@ struct FftPlan {
 // Returns false (and leaves plan->ok false) if a size is odd, > 1024 or has a
 // prime factor other than 2, 3, 5.
 bool fft_plan_create(FftPlan* plan, const int N[3]);
+// the same with the twiddle tables from a caller's allocator (released by
+// fft_plan_destroy_with through `release`)
+bool fft_plan_create_with(FftPlan* plan, const int N[3], void* (*alloc)(size_t, void*),
+                          void (*release)(void*, void*), void* stream);
+void fft_plan_destroy_with(FftPlan* plan, void (*release)(void*, void*), void* stream);
+// Fills sizes and radix plans only (no allocation, tw left null): the caller
+// points each axis's tw at L twiddles it provides (fft_twiddles_host's values).
+bool fft_plan_describe(FftPlan* plan, const int N[3]);
+// exp(-2 pi i m / L), m = 0..L-1, rounded from long double
+void fft_twiddles_host(int L, cplx* tw);
 void fft_plan_destroy(FftPlan* plan);
 bool fft_size_supported(int n);
 

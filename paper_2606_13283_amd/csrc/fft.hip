@@ -651,7 +651,14 @@ static void factor(FftAxis& ax) {
   for (int i = ax.nst; i < 8; ++i) ax.radix[i] = 1;
 }
 
-bool fft_plan_create(FftPlan* plan, const int N[3]) {
+void fft_twiddles_host(int L, cplx* tw) {
+  for (int m = 0; m < L; ++m) {
+    long double ang = 2.0L * 3.141592653589793238462643383279502884L * (long double)m / (long double)L;
+    tw[m] = cplx{(double)cosl(ang), (double)(-sinl(ang))};
+  }
+}
+
+bool fft_plan_describe(FftPlan* plan, const int N[3]) {
   std::memset(plan, 0, sizeof(*plan));
   for (int a = 0; a < 3; ++a)
     if (!fft_size_supported(N[a])) return false;
@@ -661,26 +668,47 @@ bool fft_plan_create(FftPlan* plan, const int N[3]) {
     ax.L = N[a];
     factor(ax);
     if (ax.nst > 8) return false;
-    std::vector<cplx> tw(ax.L);
-    for (int m = 0; m < ax.L; ++m) {
-      long double ang = 2.0L * 3.141592653589793238462643383279502884L * (long double)m / (long double)ax.L;
-      tw[m] = cplx{(double)cosl(ang), (double)(-sinl(ang))};
-    }
-    if (hipMalloc(&ax.tw, ax.L * sizeof(cplx)) != hipSuccess) return false;
-    if (hipMemcpy(ax.tw, tw.data(), ax.L * sizeof(cplx), hipMemcpyHostToDevice) != hipSuccess) return false;
   }
   plan->Nh = N[2] / 2 + 1;
   plan->ng = (int64_t)N[0] * N[1] * N[2];
   plan->nh = (int64_t)N[0] * N[1] * plan->Nh;
+  return true;
+}
+
+bool fft_plan_create_with(FftPlan* plan, const int N[3], void* (*alloc)(size_t, void*),
+                          void (*release)(void*, void*), void* stream) {
+  if (!fft_plan_describe(plan, N)) return false;
+  for (int a = 0; a < 3; ++a) {
+    FftAxis& ax = plan->ax[a];
+    std::vector<cplx> tw(ax.L);
+    fft_twiddles_host(ax.L, tw.data());
+    const size_t bytes = ax.L * sizeof(cplx);
+    if (alloc) {
+      ax.tw = (cplx*)alloc(bytes, stream);
+      if (!ax.tw) return false;
+    } else if (hipMalloc(&ax.tw, bytes) != hipSuccess) {
+      return false;
+    }
+    if (hipMemcpy(ax.tw, tw.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) return false;
+  }
   plan->ok = true;
   return true;
 }
 
-void fft_plan_destroy(FftPlan* plan) {
-  for (int a = 0; a < 3; ++a)
-    if (plan->ax[a].tw) (void)hipFree(plan->ax[a].tw);
+bool fft_plan_create(FftPlan* plan, const int N[3]) { return fft_plan_create_with(plan, N, nullptr, nullptr, nullptr); }
+
+void fft_plan_destroy_with(FftPlan* plan, void (*release)(void*, void*), void* stream) {
+  for (int a = 0; a < 3; ++a) {
+    if (!plan->ax[a].tw) continue;
+    if (release)
+      release(plan->ax[a].tw, stream);
+    else
+      (void)hipFree(plan->ax[a].tw);
+  }
   std::memset(plan, 0, sizeof(*plan));
 }
+
+void fft_plan_destroy(FftPlan* plan) { fft_plan_destroy_with(plan, nullptr, nullptr); }
 
 // the plane passes move the real field as 16-byte pairs
 static bool aligned16(const void* a, const void* b) { return (((uintptr_t)a | (uintptr_t)b) & 15u) == 0; }

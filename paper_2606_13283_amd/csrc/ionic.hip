@@ -102,6 +102,43 @@ __device__ inline double form_factor(double q, double Z, double rc) {
   return -Z * cos(2.0 * PI * q * rc) / (PI * q * q);
 }
 
+// Tabulated non-Coulomb part D_s at q > 0: the cubic through the nodes i-1..i+2
+// around x = q/dq (local cubic Lagrange; node -1 mirrors node 1, D_s being even
+// in q).  Returns D_s(q) and, in *dd, its derivative in q.
+__device__ inline double ff_table_eval(const double* f, double dq, double q, double* dd) {
+  const double x = q / dq;
+  const int i = (int)floor(x);
+  const double t = x - (double)i;
+  const double fm = f[i == 0 ? 1 : i - 1], f0 = f[i], f1 = f[i + 1], f2 = f[i + 2];
+  const double tp = t + 1.0, tm = t - 1.0, tmm = t - 2.0;
+  const double lm = -t * tm * tmm / 6.0, l0 = tp * tm * tmm / 2.0, l1 = -tp * t * tmm / 2.0, l2 = tp * t * tm / 6.0;
+  // derivatives of the four basis cubics in t
+  const double dm = -(3.0 * t * t - 6.0 * t + 2.0) / 6.0;
+  const double d0 = (3.0 * t * t - 4.0 * t - 1.0) / 2.0;
+  const double d1 = -(3.0 * t * t - 2.0 * t - 2.0) / 2.0;
+  const double d2 = (3.0 * t * t - 1.0) / 6.0;
+  *dd = (fm * dm + f0 * d0 + f1 * d1 + f2 * d2) / dq;
+  return fm * lm + f0 * l0 + f1 * l1 + f2 * l2;
+}
+
+// V_s(q) for q > 0 (Sec. 2.4, eq. iepseudo)
+__device__ inline double species_ff(const SpeciesInfo& sp, int s, double q) {
+  if (!sp.ff) return form_factor(q, sp.Z[s], sp.rc[s]);
+  double dd;
+  return ff_table_eval(sp.ff + (int64_t)s * sp.ff_len, sp.ff_dq, q, &dd) - sp.Z[s] / (PI * q * q);
+}
+
+// dV_s/dq for q > 0 (k2 = q^2)
+__device__ inline double species_ff_dq(const SpeciesInfo& sp, int s, double q, double k2) {
+  if (!sp.ff) {
+    const double a = 2.0 * PI * q * sp.rc[s];
+    return sp.Z[s] * (2.0 * PI * sp.rc[s] * sin(a) / k2 + 2.0 * cos(a) / (k2 * q)) / PI;
+  }
+  double dd;
+  (void)ff_table_eval(sp.ff + (int64_t)s * sp.ff_len, sp.ff_dq, q, &dd);
+  return dd + 2.0 * sp.Z[s] / (PI * k2 * q);
+}
+
 // SZ+- = sum_s Z_s S+-_s ; V^ie^(m) = sum_s V_s(|k|) (S+_s + S-_s)/2 (Hermitian part)
 __global__ void __launch_bounds__(ARCHE_BLOCK)
 k_vie_hat(const cplx* Sp, const cplx* Sm, SpeciesInfo sp, GridInfo g, cplx* SZp, cplx* SZm, cplx* vhat) {
@@ -116,7 +153,7 @@ k_vie_hat(const cplx* Sp, const cplx* Sm, SpeciesInfo sp, GridInfo g, cplx* SZp,
       const cplx a = Sp[(int64_t)s * g.nh + m], b = Sm[(int64_t)s * g.nh + m];
       zp = cadd(zp, cscale(a, sp.Z[s]));
       zm = cadd(zm, cscale(b, sp.Z[s]));
-      if (q > 0.0) v = cadd(v, cscale(cadd(a, b), 0.5 * form_factor(q, sp.Z[s], sp.rc[s])));
+      if (q > 0.0) v = cadd(v, cscale(cadd(a, b), 0.5 * species_ff(sp, s, q)));
     }
     SZp[m] = zp;
     SZm[m] = zm;
@@ -193,7 +230,7 @@ k_force_weights(const cplx* nhat, const cplx* SZp, const cplx* SZm, SpeciesInfo 
       cplx wp{0, 0}, wm{0, 0};
       if (k2 > 0.0) {
         const double q = sqrt(k2);
-        const double vs = form_factor(q, sp.Z[s], sp.rc[s]);
+        const double vs = species_ff(sp, s, q);
         const double va = sp.Z[s] * exp(-PI * PI * k2 / (alpha * alpha)) / (PI * k2);
         wp = cadd(cscale(n, vs), cscale(zp, va));
         wm = cadd(cscale(n, vs), cscale(zm, va));
@@ -290,8 +327,7 @@ k_pressure_ie(const cplx* nhat, const cplx* Sp, const cplx* Sm, SpeciesInfo sp, 
     const bool interior = iz != 0 && 2 * iz != g.N[2];
     const cplx n = nhat[m];
     for (int s = 0; s < sp.ns; ++s) {
-      const double a = 2.0 * PI * q * sp.rc[s];
-      const double dv = sp.Z[s] * (2.0 * PI * sp.rc[s] * sin(a) / k2 + 2.0 * cos(a) / (k2 * q)) / PI;
+      const double dv = species_ff_dq(sp, s, q, k2);
       const cplx b = Sp[(int64_t)s * g.nh + m];
       double t = n.x * b.x + n.y * b.y;  // Re(conj(n) S+)
       if (interior) {
@@ -390,6 +426,7 @@ unsigned grid_for(int64_t n) {
 }  // namespace
 
 double ewald_alpha(const arche_ctx* c) {
+  if (c->p.ewald_alpha > 0.0) return c->p.ewald_alpha;
   double kc = 1e300, rc = 1e300;
   for (int a = 0; a < 3; ++a) {
     kc = std::min(kc, c->g.N[a] / (2.0 * c->g.L[a]));
@@ -499,10 +536,10 @@ hipError_t ionic_shells(arche_ctx* c) {
   }
   off.push_back((int32_t)g.nh);
   c->nshell = ns;
-  if (hipMalloc(&c->shell_of, g.nh * sizeof(int32_t)) != hipSuccess) return hipErrorOutOfMemory;
-  if (hipMalloc(&c->shell_perm, g.nh * sizeof(int32_t)) != hipSuccess) return hipErrorOutOfMemory;
-  if (hipMalloc(&c->shell_off, (ns + 1) * sizeof(int32_t)) != hipSuccess) return hipErrorOutOfMemory;
-  if (hipMalloc(&c->shell_g, ns * sizeof(double)) != hipSuccess) return hipErrorOutOfMemory;
+  if (c->dalloc_.get((void**)&c->shell_of, g.nh * sizeof(int32_t), c->stream) != hipSuccess) return hipErrorOutOfMemory;
+  if (c->dalloc_.get((void**)&c->shell_perm, g.nh * sizeof(int32_t), c->stream) != hipSuccess) return hipErrorOutOfMemory;
+  if (c->dalloc_.get((void**)&c->shell_off, (ns + 1) * sizeof(int32_t), c->stream) != hipSuccess) return hipErrorOutOfMemory;
+  if (c->dalloc_.get((void**)&c->shell_g, ns * sizeof(double), c->stream) != hipSuccess) return hipErrorOutOfMemory;
   HIP_TRY(hipMemcpy(c->shell_of, shell_of.data(), g.nh * sizeof(int32_t), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(c->shell_perm, perm.data(), g.nh * sizeof(int32_t), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(c->shell_off, off.data(), (ns + 1) * sizeof(int32_t), hipMemcpyHostToDevice));

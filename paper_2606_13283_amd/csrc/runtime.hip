@@ -75,22 +75,21 @@ arche_status hip_err(arche_ctx* c, hipError_t e, const char* what) {
   } while (0)
 
 template <class T>
-hipError_t dalloc(T** p, size_t n) {
-  return hipMalloc((void**)p, std::max<size_t>(n, 1) * sizeof(T));
+hipError_t dalloc(arche_ctx* c, T** p, size_t n) {
+  return c->dalloc_.get((void**)p, std::max<size_t>(n, 1) * sizeof(T), c->stream);
 }
 
 void free_all(arche_ctx* c) {
-  void* ptrs[] = {c->Vie, c->VH, c->lap_i, c->n_i, c->n_a, c->Vi, c->lap_a, c->rtmp, c->nhat_i, c->nhat_a, c->ctmp,
+  void* ptrs[] = {c->ff_d, c->Vie, c->VH, c->lap_i, c->n_i, c->n_a, c->Vi, c->lap_a, c->rtmp, c->nhat_i, c->nhat_a, c->ctmp,
                   c->ctmp2, c->Sp, c->Sm, c->SZp, c->SZm, c->prev_nhat, c->prev_SZp, c->prev_SZm, c->shell_of,
                   c->shell_perm, c->shell_off, c->shell_g, c->pos, c->Zatom, c->forces, c->fpp, c->fpart, c->spec_d,
                   c->sp_order, c->sp_begin, c->Wp, c->Wm, c->phx, c->phy, c->phz, c->partials, c->sums, c->state,
                   c->bar, c->err_d};
-  for (void* p : ptrs)
-    if (p) (void)hipFree(p);
+  for (void* p : ptrs) c->dalloc_.put(p, c->stream);
   if (c->state_host) (void)hipHostFree(c->state_host);
   delete c->prof;
   c->prof = nullptr;
-  if (c->plan.ok) fft_plan_destroy(&c->plan);
+  fft_plan_destroy_with(&c->plan, c->dalloc_.release, (void*)c->stream);
 }
 
 arche_status validate(const arche_params* p, std::string& msg) {
@@ -120,6 +119,22 @@ arche_status validate(const arche_params* p, std::string& msg) {
   if (p->more_warmup < 0) return msg = "more_warmup must be >= 0", ARCHE_EINVAL;
   if (!(p->more_trust > 0.0)) return msg = "more_trust must be positive", ARCHE_EINVAL;
   if (p->init < ARCHE_INIT_UNIFORM || p->init > ARCHE_INIT_LEARNED) return msg = "unknown init", ARCHE_EINVAL;
+  if (!std::isfinite(p->ewald_alpha)) return msg = "ewald_alpha must be finite", ARCHE_EINVAL;
+  if (p->ff_table) {
+    if (p->ff_len < 4) return msg = "ff_len must be >= 4", ARCHE_EINVAL;
+    if (!(p->ff_dq > 0.0) || !std::isfinite(p->ff_dq)) return msg = "ff_dq must be positive", ARCHE_EINVAL;
+    for (int64_t i = 0; i < (int64_t)p->ff_len * p->n_species; ++i)
+      if (!std::isfinite(p->ff_table[i])) return msg = "ff_table holds a non-finite value", ARCHE_EINVAL;
+    // the cubic around the largest |k| of the box reads the node floor(q/dq) + 2
+    double q2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      const double kn = (p->grid[a] / 2) / p->cell[a];
+      q2 += kn * kn;
+    }
+    const double need = std::floor(std::sqrt(q2) / p->ff_dq) + 2.0;
+    if (need > (double)(p->ff_len - 1))
+      return msg = "ff_table does not reach two nodes past the largest |k| of the grid", ARCHE_EINVAL;
+  }
   return ARCHE_OK;
 }
 
@@ -194,7 +209,8 @@ arche_status evaluate(arche_ctx* c, arche_result* out) {
   double Ealpha = 0.0;
   for (int j = 0; j < c->n_atoms; ++j) {
     const int s = c->species[j];
-    Ealpha += 2.0 * PI * c->Z[s] * c->rc[s] * c->rc[s];
+    // lim_{q->0} [V_s(q) + Z_s/(pi q^2)]: 2 pi Z r_c^2 for the empty core, D_s(0) for a table
+    Ealpha += c->ff_host.empty() ? 2.0 * PI * c->Z[s] * c->rc[s] * c->rc[s] : c->ff_host[(size_t)s * c->p.ff_len];
   }
   Ealpha *= c->Ne / g.vol;
   const double Eie = e[4] + Ealpha;
@@ -325,6 +341,16 @@ arche_status solve_finish(arche_ctx* c, arche_result* out, int fallback) { retur
 arche_status solve_forces(arche_ctx* c) { return do_forces(c); }
 arche_status ctx_error(arche_ctx* c, arche_status s, const std::string& m) { return set_err(c, s, m); }
 
+namespace {
+std::mutex g_alloc_mtx;
+DevAllocator g_allocator;  // installed by arche_set_allocator (null pair: hipMalloc)
+}  // namespace
+
+DevAllocator current_allocator() {
+  std::lock_guard<std::mutex> lk(g_alloc_mtx);
+  return g_allocator;
+}
+
 extern "C" {
 
 arche_status arche_scf_init(const arche_params* p, void* hip_stream, arche_ctx** out) {
@@ -347,6 +373,9 @@ arche_status arche_scf_init(const arche_params* p, void* hip_stream, arche_ctx**
   c->p = *p;
   c->p.species = nullptr;
   c->p.Z = c->p.rc = c->p.mass = nullptr;
+  c->p.ff_table = nullptr;
+  c->dalloc_ = current_allocator();
+  if (p->ff_table) c->ff_host.assign(p->ff_table, p->ff_table + (size_t)p->ff_len * p->n_species);
   c->n_atoms = p->n_atoms;
   c->n_species = p->n_species;
   c->species.assign(p->species, p->species + p->n_atoms);
@@ -396,7 +425,8 @@ arche_status arche_scf_init(const arche_params* p, void* hip_stream, arche_ctx**
   int dev_attr = 0;
   (void)hipDeviceGetAttribute(&dev_attr, hipDeviceAttributeCooperativeLaunch, c->device);
   if (!dev_attr) return fail_init(ARCHE_EHIP, "device does not support cooperative launches");
-  if (!fft_plan_create(&c->plan, g.N)) return fail_init(ARCHE_ENOMEM, "FFT plan creation failed");
+  if (!fft_plan_create_with(&c->plan, g.N, c->dalloc_.alloc, c->dalloc_.release, (void*)c->stream))
+    return fail_init(ARCHE_ENOMEM, "FFT plan creation failed");
   c->fdt = fd_tables_device(c->device);
   if (!c->fdt) return fail_init(ARCHE_ENOMEM, "Fermi-Dirac table upload failed");
   c->coop_blocks = scf_coop_blocks(g.ng);
@@ -405,28 +435,29 @@ arche_status arche_scf_init(const arche_params* p, void* hip_stream, arche_ctx**
   const int ns = c->n_species, n = c->n_atoms;
   bool ok = true;
   for (double** f : {&c->Vie, &c->VH, &c->lap_i, &c->n_i, &c->n_a, &c->Vi, &c->lap_a, &c->rtmp})
-    ok = ok && dalloc(f, g.ng) == hipSuccess;
+    ok = ok && dalloc(c, f, g.ng) == hipSuccess;
   for (cplx** f : {&c->nhat_i, &c->nhat_a, &c->ctmp, &c->ctmp2, &c->SZp, &c->SZm, &c->prev_nhat, &c->prev_SZp,
                    &c->prev_SZm})
-    ok = ok && dalloc(f, g.nh) == hipSuccess;
-  for (cplx** f : {&c->Sp, &c->Sm, &c->Wp, &c->Wm}) ok = ok && dalloc(f, (size_t)ns * g.nh) == hipSuccess;
-  ok = ok && dalloc(&c->phx, (size_t)n * g.N[0]) == hipSuccess;
-  ok = ok && dalloc(&c->phy, (size_t)n * g.N[1]) == hipSuccess;
-  ok = ok && dalloc(&c->phz, (size_t)n * g.Nh) == hipSuccess;
-  ok = ok && dalloc(&c->pos, 3 * (size_t)n) == hipSuccess;
-  ok = ok && dalloc(&c->Zatom, (size_t)n) == hipSuccess;
-  ok = ok && dalloc(&c->forces, 3 * (size_t)n) == hipSuccess;
-  ok = ok && dalloc(&c->fpp, 3 * (size_t)n) == hipSuccess;
-  ok = ok && dalloc(&c->spec_d, (size_t)n) == hipSuccess;
-  ok = ok && dalloc(&c->sp_order, (size_t)n) == hipSuccess;
-  ok = ok && dalloc(&c->sp_begin, (size_t)ns + 1) == hipSuccess;
+    ok = ok && dalloc(c, f, g.nh) == hipSuccess;
+  for (cplx** f : {&c->Sp, &c->Sm, &c->Wp, &c->Wm}) ok = ok && dalloc(c, f, (size_t)ns * g.nh) == hipSuccess;
+  ok = ok && dalloc(c, &c->phx, (size_t)n * g.N[0]) == hipSuccess;
+  ok = ok && dalloc(c, &c->phy, (size_t)n * g.N[1]) == hipSuccess;
+  ok = ok && dalloc(c, &c->phz, (size_t)n * g.Nh) == hipSuccess;
+  ok = ok && dalloc(c, &c->pos, 3 * (size_t)n) == hipSuccess;
+  ok = ok && dalloc(c, &c->Zatom, (size_t)n) == hipSuccess;
+  ok = ok && dalloc(c, &c->forces, 3 * (size_t)n) == hipSuccess;
+  ok = ok && dalloc(c, &c->fpp, 3 * (size_t)n) == hipSuccess;
+  ok = ok && dalloc(c, &c->spec_d, (size_t)n) == hipSuccess;
+  ok = ok && dalloc(c, &c->sp_order, (size_t)n) == hipSuccess;
+  ok = ok && dalloc(c, &c->sp_begin, (size_t)ns + 1) == hipSuccess;
   c->partial_cap = (int)scf_part_offset(c) + 64 * 1024 + n + 64;
-  ok = ok && dalloc(&c->partials, (size_t)c->partial_cap) == hipSuccess;
-  ok = ok && dalloc(&c->sums, 64) == hipSuccess;
-  ok = ok && dalloc(&c->state, 1) == hipSuccess;
-  ok = ok && dalloc(&c->bar, (size_t)c->coop_blocks + 1) == hipSuccess;
-  ok = ok && dalloc(&c->err_d, 1) == hipSuccess;
-  if (ok) ok = dalloc(&c->fpart, ionic_force_partials(c)) == hipSuccess;
+  ok = ok && dalloc(c, &c->partials, (size_t)c->partial_cap) == hipSuccess;
+  ok = ok && dalloc(c, &c->sums, 64) == hipSuccess;
+  ok = ok && dalloc(c, &c->state, 1) == hipSuccess;
+  ok = ok && dalloc(c, &c->bar, (size_t)c->coop_blocks + 1) == hipSuccess;
+  ok = ok && dalloc(c, &c->err_d, 1) == hipSuccess;
+  if (ok) ok = dalloc(c, &c->fpart, ionic_force_partials(c)) == hipSuccess;
+  if (ok && !c->ff_host.empty()) ok = dalloc(c, &c->ff_d, c->ff_host.size()) == hipSuccess;
   if (ok) ok = hipHostMalloc((void**)&c->state_host, 2 * sizeof(ScfState), hipHostMallocDefault) == hipSuccess;
   if (!ok) return fail_init(ARCHE_ENOMEM, "device allocation failed");
   std::vector<int32_t> order(n), begin(ns + 1, 0);
@@ -442,8 +473,13 @@ arche_status arche_scf_init(const arche_params* p, void* hip_stream, arche_ctx**
   bool up = hipMemcpy(c->Zatom, c->Zj.data(), n * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(c->spec_d, c->species.data(), n * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(c->sp_order, order.data(), n * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
-            hipMemcpy(c->sp_begin, begin.data(), (ns + 1) * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess;
+            hipMemcpy(c->sp_begin, begin.data(), (ns + 1) * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
+            (c->ff_host.empty() || hipMemcpy(c->ff_d, c->ff_host.data(), c->ff_host.size() * sizeof(double),
+                                             hipMemcpyHostToDevice) == hipSuccess);
   if (!up) return fail_init(ARCHE_EHIP, "upload failed");
+  c->sp.ff = c->ff_d;
+  c->sp.ff_len = c->ff_host.empty() ? 0 : p->ff_len;
+  c->sp.ff_dq = c->ff_host.empty() ? 0.0 : p->ff_dq;
   if (ionic_shells(c) != hipSuccess) return fail_init(ARCHE_ENOMEM, "shell table allocation failed");
   if (fft_tune(&c->plan, c->ctmp, c->rtmp, c->stream) != hipSuccess) return fail_init(ARCHE_EHIP, "FFT tile tuning failed");
   g_live_contexts.fetch_add(1);
@@ -557,6 +593,14 @@ arche_status arche_reset_history(arche_ctx* c) {
   if (!c) return ARCHE_EINVAL;
   c->have_prev = false;
   c->have_r_prev = false;
+  return ARCHE_OK;
+}
+
+arche_status arche_set_allocator(void* (*alloc)(size_t, void*), void (*release)(void*, void*)) {
+  if ((alloc == nullptr) != (release == nullptr)) return ARCHE_EINVAL;
+  std::lock_guard<std::mutex> lk(g_alloc_mtx);
+  g_allocator.alloc = alloc;
+  g_allocator.release = release;
   return ARCHE_OK;
 }
 

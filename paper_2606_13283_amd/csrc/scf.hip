@@ -383,7 +383,8 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
     st->iter = t + 1;
     st->more_on = more;
     if (!found) st->mu_fail = 1;
-    const bool bad = !(res == res) || !found || *a.err;
+    // raised by any block's bounded wait: read through the device-coherent path
+    const bool bad = !(res == res) || !found || __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (bad) st->err = 1;
     st->done = last || bad;
   }
@@ -1018,15 +1019,15 @@ hipError_t scf_iteration(arche_ctx* c) {
   {
     ProfScope prof(PROF_SCF_ACTIVE, c->stream);
     // The kernel's all-reduces need every block resident at once.  The grid is
-    // the occupancy-sized count of one kernel alone on the device; with this
-    // context the only one in the process, nothing else can hold CUs while
-    // waiting on it (other kernels finish by themselves, then the rest of the
-    // grid is dispatched), and a plain launch saves the ~20 us a cooperative
-    // launch spends around the kernel.  With other contexts alive (another
-    // all-reduce kernel could take part of the CUs) the launch is cooperative,
-    // which guarantees residency.  Waits are bounded in any case (a time-out
+    // the occupancy-sized count of one kernel alone on the device.  A
+    // cooperative launch guarantees residency.  When the caller has declared
+    // the device its own (exclusive_device) and this context is the only one
+    // in the process, nothing else can hold CUs while waiting on the kernel
+    // (other kernels finish by themselves, then the rest of the grid is
+    // dispatched), and a plain launch saves the ~20 us a cooperative launch
+    // spends around the kernel.  Waits are bounded in any case (a time-out
     // raises the error flag instead of hanging).
-    if (g_live_contexts.load() == 1) {
+    if (c->p.exclusive_device && g_live_contexts.load() == 1) {
       if (cache)
         hipLaunchKernelGGL(k_scf_active<true>, dim3(c->coop_blocks), dim3(ARCHE_BLOCK), 0, c->stream, c->active);
       else

@@ -87,6 +87,27 @@ def test_invalid_options_rejected(lib):
         assert e.value.status == arche.EINVAL
 
 
+def test_invalid_form_factor_table_rejected(lib):
+    w = W.fcc32()
+    qmax = np.sqrt(3) * 16 / w.cell[0]  # the largest |k| of the 32^3 box
+    dq = 0.01
+    short = np.zeros((1, int(qmax / dq) + 2))  # one node short of floor(qmax/dq) + 2
+    for o in (arche.Options(ff_table=short, ff_dq=dq),
+              arche.Options(ff_table=np.zeros((1, 3)), ff_dq=10.0),
+              arche.Options(ff_table=np.zeros((1, 400)), ff_dq=0.0),
+              arche.Options(ff_table=np.full((1, 400), np.nan), ff_dq=dq),
+              arche.Options(ewald_alpha=float("inf"))):
+        with pytest.raises(arche.ArcheError) as e:
+            arche.Context(**_params(), opts=o)
+        assert e.value.status == arche.EINVAL
+
+
+def test_allocator_pair_must_be_complete(lib):
+    one = arche._ALLOC_FN(lambda n, s: None)
+    assert lib.arche_set_allocator(one, arche._RELEASE_FN()) == arche.EINVAL
+    assert lib.arche_set_allocator(arche._ALLOC_FN(), arche._RELEASE_FN()) == arche.OK
+
+
 def test_null_handles(lib):
     assert lib.arche_scf_init(None, None, None) == arche.EINVAL
     assert lib.arche_forces(None, None) == arche.EINVAL

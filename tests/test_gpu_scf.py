@@ -280,18 +280,19 @@ def test_plane_grid_iteration_parity():
 
 
 def test_plain_and_cooperative_launch_agree():
-    """The SCF kernel runs as a plain launch while its context is the only one
-    alive and as a cooperative launch otherwise; the arithmetic is the same, so
-    the two solves are bit-identical (density, F, iterations)."""
+    """With exclusive_device set, the SCF kernel runs as a plain launch while its
+    context is the only one alive and as a cooperative launch otherwise (the
+    default is always cooperative); the arithmetic is the same, so the two
+    solves are bit-identical (density, F, iterations)."""
     import gc
     gc.collect()
     L = arche.load()
     w = W.small_random(8, 20, 2.7, 5.0, seed=12)
-    ctx = arche.Context.from_workload(w, opts_of(w, init=arche.INIT_UNIFORM))
+    ctx = arche.Context.from_workload(w, opts_of(w, init=arche.INIT_UNIFORM, exclusive_device=1))
     assert L.arche_debug_live_contexts() == 1, "another context is still alive"
     r1 = ctx.solve(w.pos)
     n1 = ctx.density()
-    other = arche.Context.from_workload(w, opts_of(w, init=arche.INIT_UNIFORM))
+    other = arche.Context.from_workload(w, opts_of(w, init=arche.INIT_UNIFORM, exclusive_device=1))
     assert L.arche_debug_live_contexts() == 2
     r2 = ctx.solve(w.pos)
     n2 = ctx.density()
