@@ -27,6 +27,31 @@ arche_status arche_k_fft_r2c(const int32_t grid[3], const double *d_in, double *
  * not enter, as for any real field).  d_in is not modified.  Blocks until done. */
 arche_status arche_k_fft_c2r(const int32_t grid[3], const double *d_in, double *d_out, void *stream);
 
+/* Largest half spectrum (complex values, Nx*Ny*(Nz/2+1)) that
+ * arche_k_fft_c2r_noalloc accepts: that of a 128^3 grid (16.25 MiB of work space in
+ * the scratch array, which also holds 342 KiB of twiddle tables). */
+#define ARCHE_NOALLOC_MAX_NH 1064960
+
+/* arche_k_fft_c2r for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same transform, the same kernels and the same result, with its work
+ * copy of the spectrum and the twiddle tables in a library-owned static device
+ * array instead of a per-call hipMalloc.  The caller still owns d_in (not
+ * modified) and d_out.  Stream-ordered: it returns once the work is enqueued on
+ * `stream` and does not synchronise; d_out is ready when the stream reaches
+ * that point.
+ *   - EINVAL if grid is not supported (as arche_k_fft_c2r) or
+ *     Nx*Ny*(Nz/2+1) > ARCHE_NOALLOC_MAX_NH; nothing is enqueued then.
+ *   - The first call on a device sets up that device's copy of the array
+ *     (resolves its address, uploads the twiddle tables with one blocking
+ *     copy); later calls allocate nothing and do not block.
+ *   - The array is shared by every call on the device and keeps the last
+ *     call's contents: calls that overlap on one device (other streams, other
+ *     host threads without ordering) race on it and must be serialised by the
+ *     caller.
+ * The array holds one device's copy until the process ends. */
+arche_status arche_k_fft_c2r_noalloc(const int32_t grid[3], const double *d_in, double *d_out, void *stream);
+
 /* Complete Fermi-Dirac integrals I_j(x) = int_0^inf t^j/(exp(t-x)+1) dt
  * (Sec. 2.2, with eq. SCF1) for j = -1/2, 1/2, 3/2 at n points d_x; any output
  * may be NULL.  Blocks until done. */

@@ -198,6 +198,8 @@ def load(path: str = LIB_PATH):
     L.arche_k_fft_c2r.restype = st
     L.arche_set_allocator.argtypes = [_ALLOC_FN, _RELEASE_FN]
     L.arche_set_allocator.restype = st
+    L.arche_k_fft_c2r_noalloc.argtypes = [_ip, vp, vp, vp]
+    L.arche_k_fft_c2r_noalloc.restype = st
     L.arche_k_fermi_dirac.argtypes = [ctypes.c_int64, vp, vp, vp, vp, vp]
     L.arche_k_fermi_dirac.restype = st
     L.arche_k_fermi_dirac_derivs.argtypes = [ctypes.c_int64, vp, vp, vp, vp, vp, vp]
@@ -596,6 +598,27 @@ def fft_c2r(X, Nz):
                           ctypes.c_void_p(torch.cuda.current_stream(X.device).cuda_stream))
     if s != OK:
         raise ArcheError(s, "arche_k_fft_c2r")
+    return out
+
+
+NOALLOC_MAX_NH = 1064960  # ARCHE_NOALLOC_MAX_NH
+
+
+def fft_c2r_noalloc(X, Nz, out=None):
+    """fft_c2r through the allocation-free entry point, into `out` (allocated here
+    when None, so that callers that cannot allocate pass their own).  Enqueued on
+    torch's current stream; not synchronised."""
+    import torch
+    L = load()
+    X = X.contiguous()
+    Nx, Ny, _ = X.shape
+    if out is None:
+        out = torch.empty((Nx, Ny, Nz), dtype=torch.float64, device=X.device)
+    s = L.arche_k_fft_c2r_noalloc(_grid_arr((Nx, Ny, Nz)), ctypes.c_void_p(X.data_ptr()),
+                                  ctypes.c_void_p(out.data_ptr()),
+                                  ctypes.c_void_p(torch.cuda.current_stream(X.device).cuda_stream))
+    if s != OK:
+        raise ArcheError(s, "arche_k_fft_c2r_noalloc")
     return out
 
 

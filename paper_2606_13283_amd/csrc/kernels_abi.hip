@@ -57,6 +57,63 @@ FftPlan* plan_for(const int32_t grid[3]) {
   return p;
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of arche_k_fft_c2r_noalloc, one copy per device for the life of the
+// process: first the twiddle tables exp(-2 pi i m / L) of every supported line
+// length (each table starting on a 16-entry boundary, written once per device
+// at set-up), then the work copy of the half spectrum that the C2R passes
+// transform in place.
+constexpr int64_t tw_table_slots() {
+  int64_t n = 0;
+  for (int L = 2; L <= 1024; L += 2) {
+    int r = L;
+    while (r % 2 == 0) r /= 2;
+    while (r % 3 == 0) r /= 3;
+    while (r % 5 == 0) r /= 5;
+    if (r == 1) n += (L + 15) / 16 * 16;
+  }
+  return n;
+}
+constexpr int64_t kTwSlots = tw_table_slots();
+constexpr int64_t kScratchSlots = kTwSlots + ARCHE_NOALLOC_MAX_NH;  // complex values
+
+}  // namespace
+
+static __device__ __align__(256) double scratch[2 * kScratchSlots];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mtx;
+cplx* g_scratch_ptr[kMaxDevices] = {};  // device address of scratch, per device
+int32_t g_tw_off[1025];                 // first slot of the table of length L
+cplx g_tw_host[kTwSlots];               // host copy of the tables, built once
+
+// Set-up on the current device (first call there): resolve the array's device
+// address and upload the twiddle tables.  Returns the address or null.
+cplx* noalloc_scratch() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_noalloc_mtx);
+  if (g_scratch_ptr[dev]) return g_scratch_ptr[dev];
+  static bool host_built = false;
+  if (!host_built) {
+    int64_t off = 0;
+    for (int L = 2; L <= 1024; L += 2) {
+      if (!fft_size_supported(L)) continue;
+      g_tw_off[L] = (int32_t)off;
+      fft_twiddles_host(L, g_tw_host + off);
+      off += (L + 15) / 16 * 16;
+    }
+    host_built = true;
+  }
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+  if (hipMemcpy(p, g_tw_host, kTwSlots * sizeof(cplx), hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+  g_scratch_ptr[dev] = (cplx*)p;
+  return g_scratch_ptr[dev];
+}
+
 bool grid_ok(const int32_t* grid) {
   if (!grid) return false;
   for (int a = 0; a < 3; ++a)
@@ -88,6 +145,23 @@ arche_status arche_k_fft_c2r(const int32_t grid[3], const double* d_in, double* 
   if (e == hipSuccess) e = fft_c2r(p, work, d_out, 1.0, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(work);
+  return e == hipSuccess ? ARCHE_OK : ARCHE_EHIP;
+}
+
+arche_status arche_k_fft_c2r_noalloc(const int32_t grid[3], const double* d_in, double* d_out, void* stream) {
+  if (!grid_ok(grid) || !d_in || !d_out) return ARCHE_EINVAL;
+  FftPlan p;
+  const int N[3] = {grid[0], grid[1], grid[2]};
+  if (!fft_plan_describe(&p, N)) return ARCHE_EINVAL;
+  if (p.nh > ARCHE_NOALLOC_MAX_NH) return ARCHE_EINVAL;
+  cplx* base = noalloc_scratch();
+  if (!base) return ARCHE_EHIP;
+  for (int a = 0; a < 3; ++a) p.ax[a].tw = base + g_tw_off[p.ax[a].L];
+  p.ok = true;
+  cplx* work = base + kTwSlots;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(work, d_in, p.nh * sizeof(cplx), hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = fft_c2r(&p, work, d_out, 1.0, s);
   return e == hipSuccess ? ARCHE_OK : ARCHE_EHIP;
 }
 
