@@ -279,3 +279,55 @@ def scf(sys: System, ion: Ionic, n_init: np.ndarray, mixing="more", tol=1e-10, m
         n_i = n_a + w * dn
     return SCFResult(n_a, eta, mu, V, max_iter, r, False, hist, newt, ws)
 
+
+def scf_anderson(sys: System, ion: Ionic, n_init: np.ndarray, tol=1e-12, max_iter=2000, history=8, beta=0.5,
+                 mu0=None) -> SCFResult:
+    """The same fixed point (the Euler equation's solution, n_i = n_a) reached by
+    Anderson's acceleration of the map n_i -> n_a (Anderson 1965, in the
+    least-squares form of Pulay's DIIS): a robust generic iteration used only to
+    produce reference values of large cells quickly; the paper's own iteration is
+    `scf` above.  Residual f = n_a - n_i; with the last `history` differences of
+    inputs (dX) and residuals (dF), gamma = argmin ||f - dF gamma||_2 and
+    n_next = n_i + beta f - (dX + beta dF) gamma.  A step that would leave a
+    non-positive density is replaced by plain mixing n_i + beta f (a convex
+    combination of two positive densities) and the history restarts.  The stop
+    test and the result are those of `scf`: ||n_i - n_a||_2/||n_a||_2 < tol,
+    result n_a at its mu."""
+    cn = fd.c_n(sys.kT)
+    x = n_init.copy()
+    mu = mu0
+    hist, newt = [], []
+    dX, dF = [], []
+    x_prev = f_prev = None
+    r = float("inf")
+    n_a = eta = V = None
+    for t in range(max_iter):
+        V, _ = effective_potential(sys, ion, x)
+        mu, nit = solve_mu(sys, V, mu)
+        newt.append(nit)
+        eta = (mu - V) / sys.kT
+        n_a = cn * fd.fd_integrals(eta, ("p12",))["p12"]
+        f = n_a - x
+        r = math.sqrt(float(np.sum(f * f)) / float(np.sum(n_a * n_a)))
+        hist.append(r)
+        if r < tol:
+            return SCFResult(n_a, eta, mu, V, t + 1, r, True, hist, newt, [])
+        if x_prev is not None:
+            dX.append((x - x_prev).reshape(-1))
+            dF.append((f - f_prev).reshape(-1))
+            if len(dX) > history:
+                dX.pop(0)
+                dF.pop(0)
+        x_prev, f_prev = x, f
+        step = x + beta * f
+        if dX:
+            A = np.stack(dF, axis=1)
+            gamma = np.linalg.lstsq(A, f.reshape(-1), rcond=None)[0]
+            B = np.stack(dX, axis=1) + beta * A
+            cand = step - (B @ gamma).reshape(x.shape)
+            if float(np.min(cand)) > 0.0:
+                step = cand
+            else:
+                dX, dF = [], []
+        x = step
+    return SCFResult(n_a, eta, mu, V, max_iter, r, False, hist, newt, [])

@@ -63,7 +63,11 @@ def test_one_fixed_point_for_all_algorithms(base):
     pert = r.scf.n * (1 + 0.05 * np.cos(2 * math.pi * s.grid.points()[..., 1] / s.cell[1]))
     pert *= s.Ne / s.grid.integrate(pert)
     rg = scf.scf(s, ion, pert, mixing="more", tol=TOL)
-    for other in (rf, rg):
+    # Anderson's acceleration (the generic iteration behind the stored values
+    # of the large cells) reaches the same fixed point
+    ra = scf.scf_anderson(s, ion, scf.initial_density(s, ion)[0], tol=TOL, beta=0.3)
+    assert ra.iters < r.scf.iters
+    for other in (rf, rg, ra):
         assert other.converged
         th = thermo.evaluate(s, ion, other)
         assert abs(th.F - r.th.F) <= 1e-12 * abs(r.th.F)
