@@ -161,7 +161,29 @@ arche_status arche_forces(arche_ctx *ctx, double *forces_host);
 arche_status arche_md_step(arche_ctx *ctx, double dt, double *pos_io, double *vel_io,
                            double *forces_out_host, arche_result *out);
 
-/* Copy the converged density n_a [Nx][Ny][Nz] to dst (host if
+/* Stress tensor terms (Sec. 2.6), index of the 3x3 blocks of arche_stress's terms */
+enum {
+  ARCHE_S_KIN = 0, /* sigma^i = -(1/|Omega|) sum_j m_j v_mu v_nu (Sec. 2.6.1; zero without velocities) */
+  ARCHE_S_TF,      /* sigma^e of the Thomas-Fermi term, -(1/|Omega|) int p0 delta (Sec. 2.6.2) */
+  ARCHE_S_VW,      /* von Weizsaecker: -(lambda (2 pi)^2/|Omega|^2) sum_k k_mu k_nu |s^(k)|^2, s = sqrt(n) */
+  ARCHE_S_XC,      /* LDA xc: -(1/|Omega|) int n (v_xc - eps_xc) delta */
+  ARCHE_S_EE,      /* Hartree sigma^ee (Sec. 2.6.4) */
+  ARCHE_S_IE,      /* electron-ion sigma^ie (Sec. 2.6.5) */
+  ARCHE_S_II,      /* Ewald sigma^pp + sigma^pm + sigma^je at the context's alpha held fixed (Sec. 2.6.3) */
+  ARCHE_S_COUNT
+};
+
+/* Stress tensor Sigma = sum of the terms above at the last converged solve,
+ * each (1/|Omega|) times the derivative of its energy under a homogeneous
+ * strain at fixed fractional positions (so P = -tr(Sigma)/3 without the
+ * kinetic term reproduces arche_result.P, the Ewald part to the Ewald
+ * truncation since arche_result takes U^ii as independent of alpha).
+ * vel_host [n_atoms][3] (may be NULL: no kinetic term); sigma_host [3][3]
+ * receives the total (Hartree/bohr^3); terms_host (may be NULL)
+ * [ARCHE_S_COUNT][3][3] the terms.  ESTATE without a converged solve. */
+arche_status arche_stress(arche_ctx *ctx, const double *vel_host, double *sigma_host, double *terms_host);
+
+/* Copy the converged density n_a/* Copy the converged density n_a [Nx][Ny][Nz] to dst (host if
  * dst_on_device == 0, else device memory on the context's device).  ESTATE
  * before a solve. */
 arche_status arche_get_density(arche_ctx *ctx, double *dst, int32_t dst_on_device);
@@ -196,7 +218,24 @@ const char *arche_last_error(const arche_ctx *ctx);
 
 const char *arche_version(void);
 
-/* ---- Batched solves: many independent snapshots on one GPU ----------------
+/* ---- Equation-of-state averages (Sec. 4, Fig. pressurehistory) -----------
+ * The time average of an MD observable (pressure, energy) after dropping the
+ * thermalisation part, with the error from uncorrelated values.  Host-only.
+ * Kept values x_t, t = start .. n-1 with start = ceil(thermal_fraction n)
+ * (the paper drops about 20 %).  tau = 1/2 + sum_{t=1}^{W} C(t)/C(0),
+ * C(t) = (1/(m-t)) sum_i (x_i - mean)(x_{i+t} - mean), summed to the first
+ * window W >= 5 tau (Sokal's automatic window); values 2 tau apart count as
+ * uncorrelated: stride = max(1, ceil(2 tau)), n_eff = max(1, m / stride),
+ * sem = sqrt(var / n_eff) with var the unbiased sample variance.  EINVAL if
+ * fewer than two values remain, a kept value is not finite, or
+ * thermal_fraction is outside [0, 1). */
+typedef struct {
+  double mean, std, sem, tau;
+  int64_t n_used, n_eff, stride, start;
+} arche_eos_stat;
+arche_status arche_eos_average(const double *series, int64_t n, double thermal_fraction, arche_eos_stat *out);
+
+/* ---- Batched solves:/* ---- Batched solves: many independent snapshots on one GPU ----------------
  * A batch holds one context per snapshot (each its own cell, grid, atoms,
  * temperature and SCF options) on one stream.  arche_batch_solve runs the SCF
  * of every snapshot together: each pass of an iteration is ONE launch over all

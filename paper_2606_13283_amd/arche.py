@@ -21,6 +21,7 @@ MIX_FIXED, MIX_MORE = 0, 1
 XC_NONE, XC_LDA = 0, 1
 TERM_NAMES = ("F_TF", "K_e", "F_vW", "E_H", "F_xc", "E_ie", "U_ii", "U_pp", "U_pm", "U_je", "alpha")
 PTERM_NAMES = ("P_TF", "P_vW", "P_H", "P_xc", "P_ie", "P_ii")
+STRESS_TERMS = ("i", "TF", "vW", "xc", "ee", "ie", "ii")  # ARCHE_S_* order
 PROF_NAMES = ("scf_active", "fft_z", "fft_strided")
 DBG = dict(Vie=0, Vi=1, n_a=2, n_i=3, SZ_plus=4, SZ_minus=5, nhat_a=6, F_pp=7)
 
@@ -62,6 +63,23 @@ class Result(ctypes.Structure):
                     P_terms=dict(zip(PTERM_NAMES, list(self.pterms))), mu=self.mu, residual=self.residual,
                     w_last=self.w_last, scf_iters=self.scf_iters, newton_iters=self.newton_iters,
                     used_fallback=bool(self.used_fallback), converged=bool(self.converged))
+
+
+class EosStat(ctypes.Structure):
+    _fields_ = [("mean", ctypes.c_double), ("std", ctypes.c_double), ("sem", ctypes.c_double),
+                ("tau", ctypes.c_double), ("n_used", ctypes.c_int64), ("n_eff", ctypes.c_int64),
+                ("stride", ctypes.c_int64), ("start", ctypes.c_int64)]
+
+
+def eos_average(series, thermal_fraction=0.2):
+    """arche_eos_average: time average after the thermalisation cut, with the
+    standard error from uncorrelated values (Sec. 4)."""
+    x = _f64(series).reshape(-1)
+    st = EosStat()
+    s = load().arche_eos_average(_ptr(x), x.size, float(thermal_fraction), ctypes.byref(st))
+    if s != OK:
+        raise ArcheError(s, "arche_eos_average")
+    return {k: getattr(st, k) for k, _ in EosStat._fields_}
 
 
 _lib = None
@@ -119,6 +137,10 @@ def load(path: str = LIB_PATH):
     L.arche_forces.restype = st
     L.arche_md_step.argtypes = [vp, ctypes.c_double, _dp, _dp, _dp, ctypes.POINTER(Result)]
     L.arche_md_step.restype = st
+    L.arche_eos_average.argtypes = [_dp, ctypes.c_int64, ctypes.c_double, ctypes.POINTER(EosStat)]
+    L.arche_eos_average.restype = st
+    L.arche_stress.argtypes = [vp, _dp, _dp, _dp]
+    L.arche_stress.restype = st
     L.arche_get_density.argtypes = [vp, _dp, ctypes.c_int32]
     L.arche_get_density.restype = st
     L.arche_set_density.argtypes = [vp, _dp, ctypes.c_int32]
@@ -323,6 +345,14 @@ class Context:
         r = Result()
         self._check(self._L.arche_md_step(self._h, float(dt), _ptr(pos), _ptr(vel), _ptr(F), ctypes.byref(r)))
         return pos, vel, F, r.as_dict()
+
+    def stress(self, vel=None):
+        """(total 3x3 stress tensor, {term: 3x3}) at the last converged solve (Sec. 2.6)."""
+        sig = np.empty((3, 3))
+        terms = np.empty((len(STRESS_TERMS), 3, 3))
+        v = None if vel is None else _f64(vel, (self.n_atoms, 3))
+        self._check(self._L.arche_stress(self._h, None if v is None else _ptr(v), _ptr(sig), _ptr(terms)))
+        return sig, dict(zip(STRESS_TERMS, terms))
 
     def density(self):
         n = np.empty(self.grid)

@@ -222,6 +222,7 @@ hipError_t scf_iteration(arche_ctx* c);
 extern std::atomic<int> g_live_contexts;
 hipError_t scf_reset_state(arche_ctx* c, double mu0);
 hipError_t scf_vw_laplacian(arche_ctx* c, const double* n, double* lap);  // lap = del^2 sqrt(n)
+hipError_t scf_sqrt_spectrum(arche_ctx* c, const double* n, cplx* out);   // out = (|Omega|/N_g) DFT(sqrt n)
 hipError_t scf_energies(arche_ctx* c, double* out16);  // see scf.hip for the order
 hipError_t scf_initial_uniform(arche_ctx* c);
 hipError_t scf_initial_one_center(arche_ctx* c, int* used_fallback);  // ionic.hip
@@ -252,6 +253,8 @@ hipError_t ionic_forces(arche_ctx* c, const cplx* nhat, double* forces_dev);
 hipError_t ionic_ewald(arche_ctx* c, double* U3 /*host: pp, pm, je*/, double alpha);
 hipError_t ionic_pressure_ie(arche_ctx* c, const cplx* nhat, double* out /*host*/);
 hipError_t ionic_shells(arche_ctx* c);
+hipError_t ionic_stress_sums(arche_ctx* c, const cplx* nhat, const cplx* shat, double alpha, double* out24,
+                             double* pp6);
 size_t ionic_force_partials(const arche_ctx* c);
 double ewald_alpha(const arche_ctx* c);
 

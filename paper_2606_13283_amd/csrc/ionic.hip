@@ -423,6 +423,102 @@ unsigned grid_for(int64_t n) {
     if (e_ != hipSuccess) return e_; \
   } while (0)
 
+
+// Stress tensor sums over the full box (Sec. 2.6), six components each in the
+// order xx, yy, zz, yz, xz, xy, from the half box: a stored point m stands for
+// k and, off the k_z = 0 and Nyquist planes, for the mirror -k~ (k~ = k with its
+// Nyquist x / y components negated), whose k_mu k_nu is that of k~.
+//   ee: |n^|^2/(pi k^2) k_mu k_nu / k^2           (k != 0)
+//   vw: |s^|^2 k_mu k_nu
+//   ie: sum_s Re(conj(n^) S_s) V_s'(|k|) k_mu k_nu / |k|   (k != 0)
+//   pm: V_alpha |S_Z|^2 (pi^2/alpha^2 + 1/k^2) k_mu k_nu   (k != 0)
+// Block partials: part[(term * 6 + c) * nblk + block].
+__device__ inline void kk6(const double* k, double w, double* o) {
+  o[0] += w * k[0] * k[0];
+  o[1] += w * k[1] * k[1];
+  o[2] += w * k[2] * k[2];
+  o[3] += w * k[1] * k[2];
+  o[4] += w * k[0] * k[2];
+  o[5] += w * k[0] * k[1];
+}
+
+__global__ void __launch_bounds__(ARCHE_BLOCK)
+k_stress_recip(const cplx* nhat, const cplx* shat, const cplx* Sp, const cplx* Sm, const cplx* SZp, const cplx* SZm,
+               SpeciesInfo sp, GridInfo g, double alpha, double* part) {
+  __shared__ double sh[(ARCHE_BLOCK / 64) * 8];
+  double acc[24];
+#pragma unroll
+  for (int q = 0; q < 24; ++q) acc[q] = 0.0;
+  for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < g.nh; m += (int64_t)gridDim.x * blockDim.x) {
+    int ix, iy, iz;
+    half_index(m, g.N[1], g.Nh, ix, iy, iz);
+    double k[3];
+    kvec(ix, iy, iz, g, k);
+    const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+    const bool interior = iz != 0 && 2 * iz != g.N[2];
+    const double kt[3] = {2 * ix == g.N[0] ? -k[0] : k[0], 2 * iy == g.N[1] ? -k[1] : k[1], k[2]};
+    if (shat) {
+      const cplx sv = shat[m];
+      const double w = sv.x * sv.x + sv.y * sv.y;
+      kk6(k, w, acc + 6);
+      if (interior) kk6(kt, w, acc + 6);
+    }
+    if (k2 == 0.0) continue;
+    const double q = sqrt(k2);
+    const cplx n = nhat[m];
+    const double wee = (n.x * n.x + n.y * n.y) / (PI * k2 * k2);
+    kk6(k, wee, acc);
+    if (interior) kk6(kt, wee, acc);
+    double wp = 0.0, wm = 0.0;
+    for (int s = 0; s < sp.ns; ++s) {
+      const double dv = species_ff_dq(sp, s, q, k2) / q;
+      const cplx b = Sp[(int64_t)s * g.nh + m];
+      wp += dv * (n.x * b.x + n.y * b.y);  // Re(conj(n) S+)
+      if (interior) {
+        const cplx c = Sm[(int64_t)s * g.nh + m];
+        wm += dv * (n.x * c.x + n.y * c.y);
+      }
+    }
+    kk6(k, wp, acc + 12);
+    if (interior) kk6(kt, wm, acc + 12);
+    const double va = exp(-PI * PI * k2 / (alpha * alpha)) / (PI * k2) * (PI * PI / (alpha * alpha) + 1.0 / k2);
+    const cplx zp = SZp[m];
+    kk6(k, va * (zp.x * zp.x + zp.y * zp.y), acc + 18);
+    if (interior) {
+      const cplx zm = SZm[m];
+      kk6(kt, va * (zm.x * zm.x + zm.y * zm.y), acc + 18);
+    }
+  }
+  for (int b = 0; b < 3; ++b) {
+    block_reduce_n<8>(acc + 8 * b, 0u, sh);
+    if (threadIdx.x == 0)
+      for (int q = 0; q < 8; ++q) part[(size_t)(8 * b + q) * gridDim.x + blockIdx.x] = acc[8 * b + q];
+    __syncthreads();
+  }
+}
+
+// Ewald real-space pair tensor, per atom j: (1/2) sum_{l != j} Z_j Z_l
+// [erfc(alpha d)/d + 2 alpha/sqrt(pi) exp(-alpha^2 d^2)] d_mu d_nu / d^2 (minimum image),
+// six components per atom [j][6]
+__global__ void __launch_bounds__(ARCHE_BLOCK)
+k_ewald_pair_stress(const double* pos, const double* Zat, int n, GridInfo g, double alpha, double* out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const double xj = pos[3 * j], yj = pos[3 * j + 1], zj = pos[3 * j + 2];
+  const double c2 = 2.0 * alpha / sqrt(PI);
+  double o[6] = {0, 0, 0, 0, 0, 0};
+  for (int l = 0; l < n; ++l) {
+    if (l == j) continue;
+    double d[3] = {xj - pos[3 * l], yj - pos[3 * l + 1], zj - pos[3 * l + 2]};
+    for (int a = 0; a < 3; ++a) d[a] -= g.L[a] * rint(d[a] / g.L[a]);
+    const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    const double r = sqrt(r2);
+    const double coef = 0.5 * Zat[j] * Zat[l] * (erfc(alpha * r) / r + c2 * exp(-alpha * alpha * r2)) / r2;
+    kk6(d, coef, o);
+  }
+  for (int q = 0; q < 6; ++q) out[(size_t)q * n + j] = o[q];
+}
+
 }  // namespace
 
 double ewald_alpha(const arche_ctx* c) {
@@ -655,4 +751,30 @@ hipError_t scf_learned_proposal(arche_ctx* c) {
 hipError_t scf_initial_one_center(arche_ctx* c, int* used_fallback) {
   HIP_TRY(scf_one_center_density(c, used_fallback, nullptr, nullptr));
   return scf_prepare_input(c);
+}
+
+// Reciprocal-space and pair sums of the stress tensor at the converged state
+// (see k_stress_recip): out24 = ee[6], vw[6], ie[6], pm[6]; pp6 = the pair
+// tensor summed over atoms.  shat may be null (no von Weizsaecker term).
+hipError_t ionic_stress_sums(arche_ctx* c, const cplx* nhat, const cplx* shat, double alpha, double* out24,
+                             double* pp6) {
+  const GridInfo& g = c->g;
+  const int nbh = red_blocks(g.nh);
+  const int n = c->n_atoms;
+  double* pp = c->partials;
+  double* part = c->partials + 6 * (size_t)n;
+  hipLaunchKernelGGL(k_ewald_pair_stress, dim3((n + ARCHE_BLOCK - 1) / ARCHE_BLOCK), dim3(ARCHE_BLOCK), 0,
+                     c->stream, c->pos, c->Zatom, n, g, alpha, pp);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(finish_sums(pp, n, 6, c->sums, c->stream));
+  hipLaunchKernelGGL(k_stress_recip, dim3(nbh), dim3(ARCHE_BLOCK), 0, c->stream, nhat, shat, c->Sp, c->Sm, c->SZp,
+                     c->SZm, c->sp, g, alpha, part);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(finish_sums(part, nbh, 24, c->sums + 6, c->stream));
+  double h[30];
+  HIP_TRY(hipMemcpyAsync(h, c->sums, 30 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  for (int q = 0; q < 6; ++q) pp6[q] = h[q];
+  for (int q = 0; q < 24; ++q) out24[q] = h[6 + q];
+  return hipSuccess;
 }

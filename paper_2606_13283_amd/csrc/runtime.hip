@@ -450,7 +450,7 @@ arche_status arche_scf_init(const arche_params* p, void* hip_stream, arche_ctx**
   ok = ok && dalloc(c, &c->spec_d, (size_t)n) == hipSuccess;
   ok = ok && dalloc(c, &c->sp_order, (size_t)n) == hipSuccess;
   ok = ok && dalloc(c, &c->sp_begin, (size_t)ns + 1) == hipSuccess;
-  c->partial_cap = (int)scf_part_offset(c) + 64 * 1024 + n + 64;
+  c->partial_cap = (int)scf_part_offset(c) + 64 * 1024 + 7 * n + 64;
   ok = ok && dalloc(c, &c->partials, (size_t)c->partial_cap) == hipSuccess;
   ok = ok && dalloc(c, &c->sums, 64) == hipSuccess;
   ok = ok && dalloc(c, &c->state, 1) == hipSuccess;
@@ -613,6 +613,54 @@ void arche_scf_free(arche_ctx* c) {
   g_live_contexts.fetch_sub(1);
 }
 
+arche_status arche_stress(arche_ctx* c, const double* vel_host, double* sigma_host, double* terms_host) {
+  if (!c || !sigma_host) return set_err(c, ARCHE_EINVAL, "NULL argument");
+  if (!c->solved || !c->converged) return set_err(c, ARCHE_ESTATE, "no converged solve");
+  ProfInstall pi(c);
+  const GridInfo& g = c->g;
+  const double V = g.vol, V2 = V * V;
+  const double alpha = ewald_alpha(c);
+  const cplx* shat = nullptr;
+  if (c->p.lambda_vw != 0.0) {
+    CK(scf_sqrt_spectrum(c, c->n_a, c->ctmp));
+    shat = c->ctmp;
+  }
+  double t[24], pp[6];
+  CK(ionic_stress_sums(c, c->nhat_a, shat, alpha, t, pp));
+  const arche_result& r = c->last;
+  // per term, six components xx, yy, zz, yz, xz, xy
+  double T[ARCHE_S_COUNT][6] = {};
+  if (vel_host) {
+    for (int j = 0; j < c->n_atoms; ++j) {
+      const double m = c->mass[c->species[j]];
+      const double* v = vel_host + 3 * j;
+      const double vv[6] = {v[0] * v[0], v[1] * v[1], v[2] * v[2], v[1] * v[2], v[0] * v[2], v[0] * v[1]};
+      for (int q = 0; q < 6; ++q) T[ARCHE_S_KIN][q] -= m * vv[q] / V;
+    }
+  }
+  const double Upm_k = r.terms[ARCHE_T_UPM] + alpha / std::sqrt(PI) * c->sumZ2;  // (1/2V) sum V_a |S_Z|^2
+  for (int q = 0; q < 6; ++q) {
+    const double d = q < 3 ? 1.0 : 0.0;
+    T[ARCHE_S_TF][q] = -r.pterms[ARCHE_P_TF] * d;
+    T[ARCHE_S_XC][q] = -r.pterms[ARCHE_P_XC] * d;
+    T[ARCHE_S_VW][q] = -c->p.lambda_vw * 4.0 * PI * PI / V2 * t[6 + q];
+    T[ARCHE_S_EE][q] = t[q] / V2 - r.terms[ARCHE_T_EH] / V * d;
+    T[ARCHE_S_IE][q] = -r.terms[ARCHE_T_EIE] / V * d - t[12 + q] / V2;
+    T[ARCHE_S_II][q] = -pp[q] / V + t[18 + q] / V2 - Upm_k / V * d +
+                       PI * c->Q * c->Q / (2.0 * alpha * alpha * V2) * d;
+  }
+  static const int row[6] = {0, 1, 2, 1, 0, 0}, col[6] = {0, 1, 2, 2, 2, 1};
+  for (int a = 0; a < 9; ++a) sigma_host[a] = 0.0;
+  for (int k = 0; k < ARCHE_S_COUNT; ++k) {
+    double full[9];
+    for (int q = 0; q < 6; ++q) full[3 * row[q] + col[q]] = full[3 * col[q] + row[q]] = T[k][q];
+    for (int a = 0; a < 9; ++a) sigma_host[a] += full[a];
+    if (terms_host)
+      for (int a = 0; a < 9; ++a) terms_host[9 * k + a] = full[a];
+  }
+  return ARCHE_OK;
+}
+
 const char* arche_last_error(const arche_ctx* c) { return c ? c->err.c_str() : g_init_err.c_str(); }
 
 const char* arche_version(void) { return "arche-mi355x 0.1 (gfx950, FP64)"; }
@@ -718,3 +766,43 @@ arche_status arche_profile_reset(arche_ctx* c) {
 }
 
 }  // extern "C"
+
+// ---- equation-of-state averages (Sec. 4): thermalisation cut, mean, error from
+// uncorrelated values (integrated autocorrelation time with Sokal's window) ----
+extern "C" arche_status arche_eos_average(const double* series, int64_t n, double thermal_fraction,
+                                          arche_eos_stat* out) {
+  if (!series || !out || n < 0 || !(thermal_fraction >= 0.0 && thermal_fraction < 1.0)) return ARCHE_EINVAL;
+  const int64_t start = (int64_t)std::ceil(thermal_fraction * (double)n);
+  const int64_t m = n - start;
+  if (m < 2) return ARCHE_EINVAL;
+  const double* y = series + start;
+  for (int64_t i = 0; i < m; ++i)
+    if (!std::isfinite(y[i])) return ARCHE_EINVAL;
+  double s = 0.0;
+  for (int64_t i = 0; i < m; ++i) s += y[i];
+  const double mean = s / (double)m;
+  double ss = 0.0;
+  for (int64_t i = 0; i < m; ++i) ss += (y[i] - mean) * (y[i] - mean);
+  const double c0 = ss / (double)m;
+  double tau = 0.5;
+  if (c0 > 0.0) {
+    for (int64_t W = 1; W < m; ++W) {
+      double ct = 0.0;
+      for (int64_t i = 0; i + W < m; ++i) ct += (y[i] - mean) * (y[i + W] - mean);
+      tau += ct / (double)(m - W) / c0;
+      if ((double)W >= 5.0 * tau) break;
+    }
+  }
+  const int64_t stride = std::max<int64_t>(1, (int64_t)std::ceil(2.0 * tau));
+  const int64_t n_eff = std::max<int64_t>(1, m / stride);
+  const double var = ss / (double)(m - 1);
+  out->mean = mean;
+  out->std = std::sqrt(var);
+  out->sem = std::sqrt(var / (double)n_eff);
+  out->tau = tau;
+  out->n_used = m;
+  out->n_eff = n_eff;
+  out->stride = stride;
+  out->start = start;
+  return ARCHE_OK;
+}

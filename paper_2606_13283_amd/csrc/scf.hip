@@ -749,6 +749,14 @@ hipError_t scf_vw_laplacian(arche_ctx* c, const double* n, double* lap) {
   return fft_c2r(&c->plan, c->ctmp, lap, 1.0 / g.vol, c->stream);
 }
 
+hipError_t scf_sqrt_spectrum(arche_ctx* c, const double* n, cplx* out) {
+  const GridInfo& g = c->g;
+  hipLaunchKernelGGL(k_sqrt, dim3(grid_for(g.ng)), dim3(ARCHE_BLOCK), 0, c->stream, (const ScfState*)nullptr, 0, n,
+                     c->rtmp, g.ng);
+  HIP_TRY(hipGetLastError());
+  return fft_r2c(&c->plan, c->rtmp, out, 1.0, g.dv, c->stream);
+}
+
 // From the input density n_i: n^_i, V_H[n_i], lap(sqrt n_i).
 static hipError_t prepare_input(arche_ctx* c) {
   const GridInfo& g = c->g;
