@@ -214,6 +214,54 @@ def bench_learned(steps_train, epochs, steps_eval):
             "scf_iters_each_step": iters, "free_energy_agrees_1e-9": bool(same)}
 
 
+def bench_ablation(steps):
+    """The SCF-count ablation of Sec. 2.5.3 (Fig. convergence) on the 256-atom fcc
+    cell at 64^3 and 5 eV: MD steps with (A) the uniform initial density and
+    fixed mixing, (B) uniform and More's weight, (C) the one-center guess and
+    fixed mixing, (D) both.  Positions follow setup D's trajectory; every setup
+    solves at the same positions.  Total SCF iterations per setup, and the
+    largest relative spread of the free energy across setups at each step."""
+    import numpy as np
+
+    from paper_2606_13283_amd import arche
+    from paper_2606_13283_amd import workloads as W
+
+    w = W.fcc256()
+    setups = {"A": (arche.INIT_UNIFORM, arche.MIX_FIXED), "B": (arche.INIT_UNIFORM, arche.MIX_MORE),
+              "C": (arche.INIT_ONE_CENTER, arche.MIX_FIXED), "D": (arche.INIT_ONE_CENTER, arche.MIX_MORE)}
+    ctx = {}
+    for k, (init, mix) in setups.items():
+        o = arche.Options(w_fixed=w.w_fixed, lambda_vw=w.lam, xc=arche.XC_LDA, init=init, mixing=mix,
+                          scf_tol=1e-10, scf_max_iter=20000)
+        ctx[k] = arche.Context.from_workload(w, o)
+    m = np.array([w.mass[s] for s in w.species])[:, None]
+    r = w.pos.copy()
+    iters = {k: [] for k in setups}
+    fallback = {k: [] for k in setups}
+    spread = []
+    t0 = time.perf_counter()
+    res = {k: c.solve(r) for k, c in ctx.items()}
+    F = ctx["D"].forces()
+    r_prev = r - w.vel * w.dt + F * w.dt ** 2 / (2 * m)
+    for step in range(steps):
+        r_next = 2 * r - r_prev + F * w.dt ** 2 / m
+        res = {k: c.solve(r_next) for k, c in ctx.items()}
+        for k in setups:
+            iters[k].append(res[k]["scf_iters"])
+            fallback[k].append(int(res[k]["used_fallback"]))
+        Fs = [res[k]["F"] for k in setups]
+        spread.append((max(Fs) - min(Fs)) / abs(res["D"]["F"]))
+        F = ctx["D"].forces()
+        r_prev, r = r, r_next
+        print("[bench] ablation step %d: %s" % (step, {k: iters[k][-1] for k in setups}), file=sys.stderr, flush=True)
+    for c in ctx.values():
+        c.close()
+    return {"workload": w.name, "md_steps": steps, "scf_tol": 1e-10,
+            "total_scf_iters": {k: int(sum(v)) for k, v in iters.items()},
+            "scf_iters_each_step": iters, "one_center_fallback_each_step": {"C": fallback["C"], "D": fallback["D"]},
+            "max_rel_F_spread": max(spread) if spread else None, "seconds": time.perf_counter() - t0}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -224,6 +272,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--batch", type=int, default=64, help="snapshots of the batched-solve comparison (0: skip)")
     ap.add_argument("--learned", type=int, default=8, help="MD steps of the learned-init comparison (0: skip)")
+    ap.add_argument("--ablation", type=int, default=0,
+                    help="MD steps of the A/B/C/D SCF-count ablation on the 256-atom cell (0: skip)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device 5 times (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -362,6 +412,8 @@ def main():
         out["batch"] = bench_batch(args.batch)
     if args.learned > 0:
         out["learned_init"] = bench_learned(16, 12, args.learned)
+    if args.ablation > 0:
+        out["ablation"] = bench_ablation(args.ablation)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out))

@@ -49,7 +49,14 @@ enum {
   ARCHE_INIT_LEARNED = 3     /* the learned proposal of arche_net.h; one-center if none */
 };
 /* density mixing (Sec. 2.5.2) */
-enum { ARCHE_MIX_FIXED = 0, ARCHE_MIX_MORE = 1 };
+enum {
+  ARCHE_MIX_FIXED = 0,       /* n_o = n_a + w_fixed (n_i - n_a) throughout */
+  ARCHE_MIX_MORE = 1,        /* More's weight w = U/(U+K) with U over every potential term (Hartree, xc, vW)
+                                as the secant int (V_i - V_eff[n_a]) dn and K the secant int kT (eta(n_i) - eta_a) dn,
+                                its fall bounded by 0.05 per iteration */
+  ARCHE_MIX_MORE_PRINTED = 2 /* More's weight exactly as printed: U = int int dn dn'/|r-r'| (Hartree only),
+                                K = int dn^2/(dn_a/dmu), no bound on its fall */
+};
 /* exchange-correlation */
 enum { ARCHE_XC_NONE = 0, ARCHE_XC_LDA = 1 /* Dirac exchange + Perdew-Zunger 1981 correlation */ };
 

@@ -31,6 +31,10 @@ One iteration, with input density n_i (Sec. 2.5 and its subsections):
      never undone; and the weight may fall by at most W_MAX_DROP (0.05) per
      iteration (where xc makes U small or negative in low-density regions the
      quadratic model sends w to 0 in one step and the iteration diverges).
+     mixing="more_printed" takes the weight exactly as printed instead: U the
+     Hartree term alone, U = int int dn dn' / |r - r'|, and the second-order
+     K = int dn^2 / (dn_a/dmu), w = U / (U + K) clamped to [0, 0.995], with the
+     same switch and no bound on its fall.
   6. n_o = n_a + w Delta n becomes the next n_i.
 
 Initial densities (Sec. 2.5 and 2.5.1):
@@ -260,10 +264,17 @@ def scf(sys: System, ion: Ionic, n_init: np.ndarray, mixing="more", tol=1e-10, m
         hist.append(r)
         if r < tol:
             return SCFResult(n_a, eta, mu, V, t + 1, r, True, hist, newt, ws)
-        if mixing == "more" and not more_on and t >= warmup:
+        if mixing in ("more", "more_printed") and not more_on and t >= warmup:
             more_on = (float(np.max(np.abs(dn) / n_a)) <= more_trust
                        or (mu_prev is not None and abs(mu - mu_prev) <= MU_SETTLED * sys.kT))
-        if more_on:
+        if more_on and mixing == "more_printed":
+            # the weight exactly as printed (Sec. 2.5.2): U the Hartree interaction of
+            # dn with itself, K = int dn^2 / (dn_a/dmu), w = U / (U + K) in [0, 0.995]
+            U = 2.0 * fn.hartree_energy(g, g.forward(dn))
+            chi = cn / (2.0 * sys.kT) * v["m12"]
+            K = g.integrate(dn * dn / chi)
+            w = min(max(U / (U + K), 0.0), 0.995)
+        elif more_on:
             # U and K are the secants of the interaction and of the Thomas-Fermi
             # potential between n_a and n_i along dn (K -> int dn^2/chi as dn -> 0)
             Va, _ = effective_potential(sys, ion, n_a)

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libarche.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENOCONV, ESTATE = 0, -1, -2, -3, -4, -5
 INIT_UNIFORM, INIT_ONE_CENTER, INIT_KEEP, INIT_LEARNED = 0, 1, 2, 3
-MIX_FIXED, MIX_MORE = 0, 1
+MIX_FIXED, MIX_MORE, MIX_MORE_PRINTED = 0, 1, 2
 XC_NONE, XC_LDA = 0, 1
 TERM_NAMES = ("F_TF", "K_e", "F_vW", "E_H", "F_xc", "E_ie", "U_ii", "U_pp", "U_pm", "U_je", "alpha")
 PTERM_NAMES = ("P_TF", "P_vW", "P_H", "P_xc", "P_ie", "P_ii")

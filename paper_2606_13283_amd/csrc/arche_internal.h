@@ -125,7 +125,9 @@ struct MixWeightArgs {
   int nbv;
   int use_vw;
   double vol, dv, w_fixed;
-  ScfState* ring;  // pinned host ring [2]: the state after iteration t goes to ring[t & 1] (null: none)
+  int bound_drop;  // the weight falls by at most W_MAX_DROP per iteration (the secant form)
+  ScfState* ring;  // pinned host ring [ring_n]: the state after iteration t goes to ring[(t - 1) % ring_n] (null: none)
+  int ring_n;
 };
 struct RealMixArgs {
   const ScfState* st;
@@ -133,6 +135,7 @@ struct RealMixArgs {
   const double* n_a;
   double* sq;
   int64_t ng;
+  int sqrt_when_done;  // 1: once done, sq = sqrt(n_i) (the unfused iteration); 0: nothing
 };
 struct IterStep {
   int slot, kind;
@@ -143,6 +146,11 @@ struct IterStep {
   MixWeightArgs mw;
   RealMixArgs rm;
 };
+
+// SCF iterations per graph launch of a single-context solve, and the host ring
+// that holds the states of two launches (the host reads one launch behind)
+constexpr int ARCHE_GRAPH_ITERS = 4;
+constexpr int ARCHE_RING = 2 * ARCHE_GRAPH_ITERS;
 
 struct arche_ctx {
   arche_params p;  // copy; pointer members are not kept
@@ -185,7 +193,12 @@ struct arche_ctx {
   int partial_cap = 0;
   double *sums = nullptr;      // small result vectors
   ScfState *state = nullptr;
-  ScfState *state_host = nullptr;  // pinned mirror
+  ScfState *state_host = nullptr;  // pinned ring of SCF states, ARCHE_RING entries
+  // K whole iterations captured in a HIP graph (fused grids; built at the first solve)
+  hipGraph_t iter_graph = nullptr;
+  hipGraphExec_t iter_exec = nullptr;
+  bool graph_tried = false;
+  bool graph_plain = false;  // the captured SCF kernel launch is a plain one
   unsigned *bar = nullptr;         // grid all-reduce arrival flags [coop_blocks] + go word
   int *err_d = nullptr;
   const FdTables *fdt = nullptr;
@@ -218,6 +231,7 @@ hipError_t finish_sums(const double* partials, int nblk, int nsum, double* out, 
 
 // SCF (scf.hip)
 hipError_t scf_iteration(arche_ctx* c);
+bool scf_plain_launch(const arche_ctx* c);  // the SCF kernel's next launch is a plain one
 // contexts alive in the process (arche_scf_init .. arche_scf_free, batch members included)
 extern std::atomic<int> g_live_contexts;
 hipError_t scf_reset_state(arche_ctx* c, double mu0);

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <atomic>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -87,6 +88,10 @@ void free_all(arche_ctx* c) {
                   c->bar, c->err_d};
   for (void* p : ptrs) c->dalloc_.put(p, c->stream);
   if (c->state_host) (void)hipHostFree(c->state_host);
+  if (c->iter_exec) (void)hipGraphExecDestroy(c->iter_exec);
+  if (c->iter_graph) (void)hipGraphDestroy(c->iter_graph);
+  c->iter_exec = nullptr;
+  c->iter_graph = nullptr;
   delete c->prof;
   c->prof = nullptr;
   fft_plan_destroy_with(&c->plan, c->dalloc_.release, (void*)c->stream);
@@ -114,7 +119,8 @@ arche_status validate(const arche_params* p, std::string& msg) {
   if (p->xc != ARCHE_XC_NONE && p->xc != ARCHE_XC_LDA) return msg = "unknown xc", ARCHE_EINVAL;
   if (!(p->scf_tol > 0.0)) return msg = "scf_tol must be positive", ARCHE_EINVAL;
   if (p->scf_max_iter < 1) return msg = "scf_max_iter must be >= 1", ARCHE_EINVAL;
-  if (p->mixing != ARCHE_MIX_FIXED && p->mixing != ARCHE_MIX_MORE) return msg = "unknown mixing", ARCHE_EINVAL;
+  if (p->mixing != ARCHE_MIX_FIXED && p->mixing != ARCHE_MIX_MORE && p->mixing != ARCHE_MIX_MORE_PRINTED)
+    return msg = "unknown mixing", ARCHE_EINVAL;
   if (!(p->w_fixed >= 0.0 && p->w_fixed < 1.0)) return msg = "w_fixed must be in [0, 1)", ARCHE_EINVAL;
   if (p->more_warmup < 0) return msg = "more_warmup must be >= 0", ARCHE_EINVAL;
   if (!(p->more_trust > 0.0)) return msg = "more_trust must be positive", ARCHE_EINVAL;
@@ -159,41 +165,105 @@ arche_status collect_state(arche_ctx* c, arche_result* out) {
   return ARCHE_OK;
 }
 
-// SCF loop: one queued iteration ahead of the convergence poll.  The state was
-// reset by begin_solve; the last iteration raises done by itself.  The polled
-// states are kept as the solve's convergence history.
+// K whole iterations (the cooperative kernel and every pass) captured in one
+// HIP graph, on grids whose passes all stop by themselves once the solve is done
+// (so iterations past convergence cost only their launches).  Capture failure
+// leaves the context on the launch-by-launch loop.
+bool build_iteration_graph(arche_ctx* c) {
+  c->graph_tried = true;
+  scf_build_iteration(c);
+  if (!c->fused) return false;
+  const char* env = std::getenv("ARCHE_GRAPH");
+  if (env && env[0] == '0') return false;
+  if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  hipError_t e = hipSuccess;
+  for (int it = 0; it < ARCHE_GRAPH_ITERS && e == hipSuccess; ++it) e = scf_iteration(c);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+  if (e == hipSuccess && e2 == hipSuccess && g) {
+    hipGraphExec_t x = nullptr;
+    if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) == hipSuccess) {
+      c->iter_graph = g;
+      c->iter_exec = x;
+      c->graph_plain = scf_plain_launch(c);
+      return true;
+    }
+  }
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipGetLastError();
+  return false;
+}
+
+// SCF loop.  Work is enqueued in units (a graph launch of ARCHE_GRAPH_ITERS
+// iterations, or single iterations for the tail below scf_max_iter and when
+// timing kernels), one unit ahead of the convergence poll: after enqueuing unit
+// u the host waits for unit u-1 and reads its iterations' states from the pinned
+// ring (the weight kernel of iteration t writes ring[(t-1) % ARCHE_RING]; two
+// units fit).  The state was reset by begin_solve; the iteration that meets the
+// tolerance raises done and everything after it does nothing.  The polled states
+// are kept as the solve's convergence history.
 arche_status run_scf(arche_ctx* c, arche_result* out) {
   c->hist.clear();
+  if (c->iter_exec && c->graph_plain != scf_plain_launch(c)) {
+    // the launch mode of the SCF kernel changed (contexts came or went): capture again
+    (void)hipGraphExecDestroy(c->iter_exec);
+    (void)hipGraphDestroy(c->iter_graph);
+    c->iter_exec = nullptr;
+    c->iter_graph = nullptr;
+    c->graph_tried = false;
+  }
+  if (!c->graph_tried && !c->prof) build_iteration_graph(c);
+  const bool graph = c->iter_exec && !c->prof;
   hipEvent_t ev[2];
   CK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
   CK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
-  ScfState* ring = c->state_host;  // [2] pinned
+  const ScfState* ring = c->state_host;
+  const int max_iter = c->p.scf_max_iter;
   bool stop = false;
-  int t = 0;
-  for (; t < c->p.scf_max_iter && !stop; ++t) {
-    // the iteration's weight kernel writes its state to ring[t & 1] (pinned)
-    hipError_t e = scf_iteration(c);
-    if (e == hipSuccess) e = hipEventRecord(ev[t & 1], c->stream);
-    if (e == hipSuccess && t >= 1) {
-      e = hipEventSynchronize(ev[(t - 1) & 1]);
-      if (e == hipSuccess) {
-        c->hist.push_back(ring[(t - 1) & 1]);
-        if (ring[(t - 1) & 1].done) stop = true;
+  int launched = 0, read = 0, unit = 0;
+  int unit_end[2] = {0, 0};
+  // read the states of iterations read+1 .. upto from the ring
+  auto consume = [&](int upto) {
+    for (int j = read + 1; j <= upto && !stop; ++j) {
+      const ScfState& s = ring[(j - 1) % ARCHE_RING];
+      if (s.iter != j) {  // iteration j did nothing: the solve ended before it
+        stop = true;
+        break;
       }
+      c->hist.push_back(s);
+      read = j;
+      if (s.done) stop = true;
     }
-    if (e != hipSuccess) {
-      (void)hipEventDestroy(ev[0]);
-      (void)hipEventDestroy(ev[1]);
-      return hip_err(c, e, "scf iteration");
+  };
+  hipError_t e = hipSuccess;
+  while (!stop && launched < max_iter && e == hipSuccess) {
+    if (graph && launched + ARCHE_GRAPH_ITERS <= max_iter) {
+      e = hipGraphLaunch(c->iter_exec, c->stream);
+      launched += ARCHE_GRAPH_ITERS;
+    } else {
+      e = scf_iteration(c);
+      launched += 1;
     }
+    if (e == hipSuccess) e = hipEventRecord(ev[unit & 1], c->stream);
+    unit_end[unit & 1] = launched;
+    if (e == hipSuccess && unit >= 1) {
+      e = hipEventSynchronize(ev[(unit - 1) & 1]);
+      if (e == hipSuccess) consume(unit_end[(unit - 1) & 1]);
+    }
+    ++unit;
   }
-  // stopped by the iteration cap: the last iteration's state is still to be kept
-  if (!stop && t >= 1) {
-    hipError_t e = hipEventSynchronize(ev[(t - 1) & 1]);
-    if (e == hipSuccess) c->hist.push_back(ring[(t - 1) & 1]);
+  // the last unit (stopped by the iteration cap, or done inside it)
+  if (e == hipSuccess && !stop && unit >= 1) {
+    e = hipEventSynchronize(ev[(unit - 1) & 1]);
+    if (e == hipSuccess) consume(unit_end[(unit - 1) & 1]);
   }
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   (void)hipEventDestroy(ev[0]);
   (void)hipEventDestroy(ev[1]);
+  if (e != hipSuccess) return hip_err(c, e, "scf iteration");
   return collect_state(c, out);
 }
 
@@ -458,7 +528,7 @@ arche_status arche_scf_init(const arche_params* p, void* hip_stream, arche_ctx**
   ok = ok && dalloc(c, &c->err_d, 1) == hipSuccess;
   if (ok) ok = dalloc(c, &c->fpart, ionic_force_partials(c)) == hipSuccess;
   if (ok && !c->ff_host.empty()) ok = dalloc(c, &c->ff_d, c->ff_host.size()) == hipSuccess;
-  if (ok) ok = hipHostMalloc((void**)&c->state_host, 2 * sizeof(ScfState), hipHostMallocDefault) == hipSuccess;
+  if (ok) ok = hipHostMalloc((void**)&c->state_host, ARCHE_RING * sizeof(ScfState), hipHostMallocDefault) == hipSuccess;
   if (!ok) return fail_init(ARCHE_ENOMEM, "device allocation failed");
   std::vector<int32_t> order(n), begin(ns + 1, 0);
   {

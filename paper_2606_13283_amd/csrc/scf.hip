@@ -100,7 +100,8 @@ __device__ inline void vxc_group(const double* n, double* v) {
 template <bool CACHE, bool ACTIVE>
 __device__ inline void chunk_sums(const ActiveArgs& a, int64_t c, const double* vls, const double* xls, double mu,
                                   double ikT, const FdLds& fdl, double* sh) {
-  const bool more = a.mixing == ARCHE_MIX_MORE;
+  const bool more = a.mixing == ARCHE_MIX_MORE;  // secant K and U_xc
+  const bool printed = a.mixing == ARCHE_MIX_MORE_PRINTED;  // K = int dn^2 / (dn_a/dmu)
   const double icn = 1.0 / a.cn;
   constexpr int D = ACTIVE ? 3 : 1;
   double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -151,7 +152,12 @@ __device__ inline void chunk_sums(const ActiveArgs& a, int64_t c, const double* 
 #pragma unroll
         for (int g = 0; g < PG; ++g) acc[4] += ok[g] ? a.kT * sh_[g] * dn[g] : 0.0;  // kT (eta_i - eta_a) dn
       }
-      if (a.xc) {
+      if (printed) {
+        // dn_a/dmu = (c_n / kT) dI_{1/2}/deta
+#pragma unroll
+        for (int g = 0; g < PG; ++g) acc[4] += ok[g] ? dn[g] * dn[g] * a.kT / (a.cn * d[g][1]) : 0.0;
+      }
+      if (a.xc && more) {
         double va[PG], vi[PG];
         vxc_group(na, va);
         if (CACHE) {
@@ -367,7 +373,7 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
 
   if (lb == 0 && threadIdx.x == 0) {
     int more = st->more_on;
-    if (a.mixing == ARCHE_MIX_MORE && !more && t >= a.warmup &&
+    if (a.mixing != ARCHE_MIX_FIXED && !more && t >= a.warmup &&
         (MX <= a.trust || fabs(mu - mu_prev) <= MU_SETTLED * kT))
       more = 1;
     st->mu = mu;
@@ -484,7 +490,7 @@ __device__ inline void state_to_ring(const MixWeightArgs& m, ScfState* copy) {
   __syncthreads();
   const int k = threadIdx.x;
   if (k < STATE_WORDS) {
-    uint64_t* dst = (uint64_t*)(m.ring + ((copy->iter - 1) & 1));
+    uint64_t* dst = (uint64_t*)(m.ring + (copy->iter - 1) % m.ring_n);
     __hip_atomic_store(dst + k, ((const uint64_t*)copy)[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
@@ -511,7 +517,7 @@ __device__ inline void mix_weight_body(const MixWeightArgs& m, double* sh, ScfSt
         w = U / (U + st->K);
         w = fmin(fmax(w, 0.0), 0.995);
         // at most W_MAX_DROP below the previous weight (st->w)
-        w = fmax(w, st->w - W_MAX_DROP);
+        if (m.bound_drop) w = fmax(w, st->w - W_MAX_DROP);
         if (!(w == w)) w = m.w_fixed;
       }
       st->w = w;
@@ -531,10 +537,12 @@ __global__ void __launch_bounds__(ARCHE_BLOCK) k_mix_weight_batch(const MixWeigh
   mix_weight_body(m, sh, &copy);
 }
 
-// n^_o = n^_a + w (n^_i - n^_a) -> nhat_i;  tmp = n^_o / (pi k^2) (0 at k = 0)
+// n^_o = n^_a + w (n^_i - n^_a) -> nhat_i;  tmp = n^_o / (pi k^2) (0 at k = 0).
+// Once the solve is done n^_i stays and tmp = n^_i / (pi k^2), so that the
+// C2R that follows reproduces V_H[n_i] instead of overwriting it.
 __global__ void __launch_bounds__(ARCHE_BLOCK)
 k_spec_mix(const ScfState* st, cplx* nhat_i, const cplx* nhat_a, cplx* tmp, GridInfo g) {
-  if (st->done) return;
+  const bool done = st->done;
   const double w = st->w;
   for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < g.nh; m += (int64_t)gridDim.x * blockDim.x) {
     int ix, iy, iz;
@@ -542,15 +550,22 @@ k_spec_mix(const ScfState* st, cplx* nhat_i, const cplx* nhat_a, cplx* tmp, Grid
     const double kx = box_k(ix, g.N[0], g.L[0]), ky = box_k(iy, g.N[1], g.L[1]), kz = (double)iz / g.L[2];
     const double k2 = kx * kx + ky * ky + kz * kz;
     const cplx a = nhat_a[m];
-    const cplx o = cadd(a, cscale(csub(nhat_i[m], a), w));
-    nhat_i[m] = o;
+    const cplx o = done ? nhat_i[m] : cadd(a, cscale(csub(nhat_i[m], a), w));
+    if (!done) nhat_i[m] = o;
     tmp[m] = k2 > 0.0 ? cscale(o, 1.0 / (PI * k2)) : cplx{0.0, 0.0};
   }
 }
 
 // n_o = n_a + w (n_i - n_a) -> n_i;  sq = sqrt(n_o)   (block bid of nb)
 __device__ inline void real_mix_body(const RealMixArgs& r, unsigned bid, unsigned nb) {
-  if (r.st->done) return;
+  if (r.st->done) {
+    // the unfused iteration's later transforms run anyway: sq = sqrt(n_i) keeps
+    // lap sqrt(n_i) as it is (the fused passes stop by themselves instead)
+    if (r.sqrt_when_done)
+      for (int64_t i = (int64_t)bid * blockDim.x + threadIdx.x; i < r.ng; i += (int64_t)nb * blockDim.x)
+        r.sq[i] = sqrt(r.n_i[i]);
+    return;
+  }
   const double w = r.st->w;
   for (int64_t i = (int64_t)bid * blockDim.x + threadIdx.x; i < r.ng; i += (int64_t)nb * blockDim.x) {
     const double na = r.n_a[i];
@@ -929,7 +944,8 @@ void scf_build_iteration(arche_ctx* c) {
   w.slot = SLOT_WEIGHT;
   w.kind = STEP_WEIGHT;
   w.nblocks = 1;
-  w.mw = MixWeightArgs{c->state, part_h, nbh, part_v, nbv, (int)(more && vw), g.vol, g.dv, p.w_fixed, c->state_host};
+  w.mw = MixWeightArgs{c->state, part_h, nbh, part_v, nbv, (int)(more && vw), g.vol, g.dv, p.w_fixed, (int)more,
+                       c->state_host, ARCHE_RING};
   c->steps.push_back(w);
   if (pair && vw) {
     FftPass pe[3], pf[3];
@@ -956,7 +972,7 @@ void scf_build_iteration(arche_ctx* c) {
     r.slot = SLOT_REAL_MIX;
     r.kind = STEP_REAL_MIX;
     r.nblocks = scf_real_mix_blocks(g.ng);
-    r.rm = RealMixArgs{c->state, c->n_i, c->n_a, c->rtmp, g.ng};
+    r.rm = RealMixArgs{c->state, c->n_i, c->n_a, c->rtmp, g.ng, 0};
     c->steps.push_back(r);
   }
 }
@@ -1000,15 +1016,15 @@ static hipError_t scf_iteration_rest_plain(arche_ctx* c) {
   hipLaunchKernelGGL(k_uh_partial, dim3(nbh), dim3(ARCHE_BLOCK), 0, c->stream, (const ScfState*)c->state, c->nhat_i,
                      c->nhat_a, g, part_h);
   HIP_TRY(hipGetLastError());
-  const MixWeightArgs mw{c->state, part_h, nbh, part_v, nbr, (int)(more && vw), g.vol, g.dv, p.w_fixed,
-                         c->state_host};
+  const MixWeightArgs mw{c->state, part_h, nbh, part_v, nbr, (int)(more && vw), g.vol, g.dv, p.w_fixed, (int)more,
+                         c->state_host, ARCHE_RING};
   hipLaunchKernelGGL(k_mix_weight, dim3(1), dim3(ARCHE_BLOCK), 0, c->stream, mw);
   HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_spec_mix, dim3(grid_for(g.nh)), dim3(ARCHE_BLOCK), 0, c->stream, (const ScfState*)c->state,
                      c->nhat_i, c->nhat_a, c->ctmp, g);
   HIP_TRY(hipGetLastError());
   HIP_TRY(fft_c2r(&c->plan, c->ctmp, c->VH, 1.0 / g.vol, c->stream));
-  const RealMixArgs rm{c->state, c->n_i, c->n_a, c->rtmp, g.ng};
+  const RealMixArgs rm{c->state, c->n_i, c->n_a, c->rtmp, g.ng, 1};
   hipLaunchKernelGGL(k_real_mix, dim3(grid_for(g.ng)), dim3(ARCHE_BLOCK), 0, c->stream, rm);
   HIP_TRY(hipGetLastError());
   if (vw) {
@@ -1019,6 +1035,8 @@ static hipError_t scf_iteration_rest_plain(arche_ctx* c) {
   }
   return hipSuccess;
 }
+
+bool scf_plain_launch(const arche_ctx* c) { return c->p.exclusive_device && g_live_contexts.load() == 1; }
 
 hipError_t scf_iteration(arche_ctx* c) {
   scf_build_iteration(c);
@@ -1035,7 +1053,7 @@ hipError_t scf_iteration(arche_ctx* c) {
     // dispatched), and a plain launch saves the ~20 us a cooperative launch
     // spends around the kernel.  Waits are bounded in any case (a time-out
     // raises the error flag instead of hanging).
-    if (c->p.exclusive_device && g_live_contexts.load() == 1) {
+    if (scf_plain_launch(c)) {
       if (cache)
         hipLaunchKernelGGL(k_scf_active<true>, dim3(c->coop_blocks), dim3(ARCHE_BLOCK), 0, c->stream, c->active);
       else

@@ -86,13 +86,16 @@ def static(name, paper_iteration=False, full_density=False):
     th = thermo.evaluate(s, ion, res, forces=True, atoms=atoms)
     idx = np.arange(int(np.prod(s.shape))) if full_density else sample_points(s.shape, 11)
     out = dict(workload=w.name, grid=list(w.grid), cell=list(w.cell), scf_tol=TOL, init="uniform",
-               w_fixed=w.w_fixed, oracle_iteration="more" if paper_iteration else "anderson",
-               oracle_iters=res.iters, residual=res.residual, mu=res.mu,
+               w_fixed=w.w_fixed, residual=res.residual, mu=res.mu,
                **thermo_dict(th),
                force_atoms=list(range(n_atoms)) if atoms is None else atoms,
                forces=th.forces.tolist(),
                density_index=idx.tolist(), density=res.n.reshape(-1)[idx].tolist(),
                oracle_seconds=dict(ionic_setup=t_ion, scf=t_scf))
+    if paper_iteration:
+        out.update(oracle_iteration="more", oracle_iters=res.iters)
+    else:
+        out.update(oracle_iters_anderson=res.iters)
     return out
 
 

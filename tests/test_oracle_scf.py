@@ -46,14 +46,16 @@ def test_more_weight_closed_form():
     x = s.grid.points()[..., 0]
     eps = 1e-6
     n_i = n0 * (1 + eps * np.cos(2 * math.pi * 2 * x / L))
-    r = scf.scf(s, ion, n_i, mixing="more", warmup=0, more_trust=1e30, max_iter=1, tol=0.0)
     eta0 = fd.I_p12_inverse(n0 / fd.c_n(s.kT))
     chi = fd.c_n(s.kT) / (2 * s.kT) * fd.I_m12(np.array([eta0]))[0]
     G = 2 * math.pi * 2 / L
     g_ = chi * 4 * math.pi / G ** 2
-    assert abs(r.weights[0] - g_ / (1 + g_)) <= 1e-5
-    n_o = r.n + r.weights[0] * (n_i - r.n)
-    assert np.max(np.abs(n_o - n0)) <= 1e-3 * eps * n0
+    # the secant weight (default) and the weight exactly as printed agree here
+    for mixing in ("more", "more_printed"):
+        r = scf.scf(s, ion, n_i, mixing=mixing, warmup=0, more_trust=1e30, max_iter=1, tol=0.0)
+        assert abs(r.weights[0] - g_ / (1 + g_)) <= 1e-5, mixing
+        n_o = r.n + r.weights[0] * (n_i - r.n)
+        assert np.max(np.abs(n_o - n0)) <= 1e-3 * eps * n0, mixing
 
 
 def test_one_fixed_point_for_all_algorithms(base):
