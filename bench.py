@@ -31,6 +31,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6  # vector FP64: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
+# algorithmic FP64 flops per grid point of the SCF kernel: one Fermi-Dirac
+# evaluation pass (I_{1/2} with its derivative and the sums) ~130, the
+# potential assembly with LDA xc ~60; the kernel makes 1 + m passes, m the
+# Newton passes that confirm mu
+FLOP_PER_FD_PASS = 130.0
+FLOP_ASSEMBLY_XC = 60.0
+# algorithmic HBM bytes per grid point of one whole SCF iteration (every pass
+# at its one-read-one-write minimum, von Weizsaecker and More mixing included)
+ITER_BYTES_PER_POINT = 216.0
 METRIC = "SCF iters/s + wall s per MD step (plain vs learned-init/batched), 1024 Al, 128³"
 
 
@@ -48,6 +58,22 @@ def kernel_bytes(name, ng, nh, newton_per_launch):
     if name == "fft_strided":
         return 2.0 * nh * 16.0  # half spectrum read and written in place
     raise KeyError(name)
+
+
+def counter_flops_for(name):
+    """FP64 flops per launch from the committed rocprofv3 counter run
+    (SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes), or None when absent or stale."""
+    path = os.path.join(ROOT, "profiles", "flops_%s.json" % name)
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+        src = os.path.join(ROOT, d["source"])
+        if hashlib.sha256(open(src, "rb").read()).hexdigest() != d["source_sha256"]:
+            return None
+        return float(d["fp64_flops_per_launch"])
+    except Exception:
+        return None
 
 
 def traffic_for(name):
@@ -182,24 +208,31 @@ def bench_learned(steps_train, epochs, steps_eval):
     t_train = time.perf_counter() - t0
     n_train_steps = epochs * len(data)
     w = W.fcc256_at(5.0, seed=300)
-    trs = {"plain": LN.Trajectory(w), "previous_density": LN.Trajectory(w, init=arche.INIT_KEEP),
-           "learned": LN.Trajectory(w, init=arche.INIT_LEARNED, net=net)}
-    wall = {k: 0.0 for k in trs}
-    iters = {k: [] for k in trs}
-    Fs = {k: [] for k in trs}
-    for _ in range(steps_eval):
-        r_next = trs["plain"].next_positions()
-        for k, tr in trs.items():
+    # one variant at a time, each with only its own context alive, at the positions
+    # of the plain trajectory (several live contexts make one of them run slower)
+    kinds = {"plain": arche.INIT_ONE_CENTER, "previous_density": arche.INIT_KEEP, "learned": arche.INIT_LEARNED}
+    wall = {k: 0.0 for k in kinds}
+    iters = {k: [] for k in kinds}
+    Fs = {k: [] for k in kinds}
+    positions = None
+    for k, init in kinds.items():
+        tr = LN.Trajectory(w, init=init, net=net if k == "learned" else None)
+        if positions is None:
+            positions = []
+        for step in range(steps_eval):
             if k == "previous_density":
                 tr.ctx.set_density(tr.ctx.density())
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            res, _ = tr.step(r_next)
+            if k == "plain":
+                res, _ = tr.step()
+                positions.append(tr.pos.copy())
+            else:
+                res = tr.solve_at(positions[step])
             torch.cuda.synchronize()
             wall[k] += time.perf_counter() - t0
             iters[k].append(res["scf_iters"])
             Fs[k].append(res["F"])
-    for tr in trs.values():
         tr.close()
     net.close()
     same = all(abs(a - b) <= 1e-9 * abs(a) for k in ("previous_density", "learned") for a, b in zip(Fs["plain"], Fs[k]))
@@ -382,9 +415,26 @@ def main():
     dom = "scf_active"
     d = kernels[dom]
     traffic = traffic_for(dom)
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": d["GBps"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": d["GBps"] / PEAK_HBM_GBS, "traffic": traffic,
-                "alg_bytes_per_launch": d["alg_bytes_per_launch"], "avg_launch_us": d["avg_us"]}
+    # the SCF kernel is bound by FP64 arithmetic (Fermi-Dirac evaluations), not
+    # HBM: price it against the FP64 vector peak with its algorithmic flops
+    flops = ng * (FLOP_PER_FD_PASS * (1.0 + newton_per_launch) + FLOP_ASSEMBLY_XC)
+    tflops = flops / (d["avg_us"] * 1e-6) / 1e12
+    roofline = {"bound": "alu", "kernel": dom, "achieved": tflops, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": tflops / PEAK_FP64_TFLOPS, "traffic": traffic,
+                "alg_flops_per_launch": flops, "newton_passes_per_launch": newton_per_launch,
+                "counter_fp64_flops_per_launch": counter_flops_for(dom),
+                "alg_bytes_per_launch": d["alg_bytes_per_launch"], "hbm_GBps": d["GBps"],
+                "hbm_frac": d["GBps"] / PEAK_HBM_GBS, "avg_launch_us": d["avg_us"]}
+    # the whole iteration against HBM: kernel time per iteration of the timed
+    # classes (one untimed step with every class bracketed)
+    n_it = max(res["scf_iters"], 1)
+    cls = {k: {"us_per_iter": 1e3 * v["total_ms"] / n_it, "launches_per_iter": v["launches"] / n_it}
+           for k, v in kernels_step.items()}
+    it_us = sum(v["us_per_iter"] for v in cls.values())
+    iteration = {"kernel_us_per_iter": it_us, "alg_bytes_per_iter": ITER_BYTES_PER_POINT * ng,
+                 "hbm_GBps": ITER_BYTES_PER_POINT * ng / (it_us * 1e-6) / 1e9,
+                 "hbm_frac": ITER_BYTES_PER_POINT * ng / (it_us * 1e-6) / 1e9 / PEAK_HBM_GBS,
+                 "wall_us_per_iter": 1e6 * wall / max(iters, 1), "classes": cls}
     value = iters / wall
     out = {
         "metric": METRIC, "value": value, "unit": "SCF iters/s", "n_gpus": 1, "steps": args.steps,
@@ -406,6 +456,7 @@ def main():
         "kernels": kernels,
         "kernels_all_classes_one_untimed_step": kernels_step,
         "roofline": roofline,
+        "iteration_roofline": iteration,
         "fft_tile_variants": tiles,
     }
     if args.batch > 0:

@@ -190,6 +190,14 @@ enum {
  * [ARCHE_S_COUNT][3][3] the terms.  ESTATE without a converged solve. */
 arche_status arche_stress(arche_ctx *ctx, const double *vel_host, double *sigma_host, double *terms_host);
 
+/* The positions r(t+dt) that arche_md_step would move to from pos_host with
+ * vel_host (the Verlet update of Sec. 2.1 with the forces of the converged
+ * solve at pos_host and the context's r(t-dt), or the Taylor start when it has
+ * none), into next_host [n_atoms][3]; nothing is solved and the context's
+ * state is unchanged.  ESTATE without a converged solve at exactly pos_host. */
+arche_status arche_md_predict(arche_ctx *ctx, double dt, const double *pos_host, const double *vel_host,
+                              double *next_host);
+
 /* Copy the converged density n_a/* Copy the converged density n_a [Nx][Ny][Nz] to dst (host if
  * dst_on_device == 0, else device memory on the context's device).  ESTATE
  * before a solve. */

@@ -101,6 +101,17 @@ void arche_net_free(arche_net *net);
  * set.  The context does not own the net. */
 arche_status arche_set_init_net(arche_ctx *ctx, arche_net *net);
 
+/* The network's guide for the next MD step, without solving: G = n0 + the
+ * one-center superposition's change (Sec. 2.5.1's profile from the context's
+ * converged step, applied to the structure-factor change from the converged
+ * positions to next_pos_host), into guide_host [Nx][Ny][Nz].  Training
+ * samples pair it with the previous converged density and the density the next
+ * solve converges to.  The converged state, its positions and forces stay as
+ * they were; the context's input density (used by ARCHE_INIT_KEEP) is
+ * replaced by the plain guess at next_pos_host.  ESTATE without a converged
+ * step. */
+arche_status arche_learned_guide(arche_ctx *ctx, const double *next_pos_host, double *guide_host);
+
 #ifdef __cplusplus
 }
 #endif

@@ -139,6 +139,10 @@ def load(path: str = LIB_PATH):
     L.arche_md_step.restype = st
     L.arche_eos_average.argtypes = [_dp, ctypes.c_int64, ctypes.c_double, ctypes.POINTER(EosStat)]
     L.arche_eos_average.restype = st
+    L.arche_md_predict.argtypes = [vp, ctypes.c_double, _dp, _dp, _dp]
+    L.arche_md_predict.restype = st
+    L.arche_learned_guide.argtypes = [vp, _dp, _dp]
+    L.arche_learned_guide.restype = st
     L.arche_stress.argtypes = [vp, _dp, _dp, _dp]
     L.arche_stress.restype = st
     L.arche_get_density.argtypes = [vp, _dp, ctypes.c_int32]
@@ -345,6 +349,21 @@ class Context:
         r = Result()
         self._check(self._L.arche_md_step(self._h, float(dt), _ptr(pos), _ptr(vel), _ptr(F), ctypes.byref(r)))
         return pos, vel, F, r.as_dict()
+
+    def md_predict(self, dt, pos, vel):
+        """r(t+dt) that md_step would move to (no solve)."""
+        pos = _f64(pos, (self.n_atoms, 3))
+        vel = _f64(vel, (self.n_atoms, 3))
+        out = np.empty((self.n_atoms, 3))
+        self._check(self._L.arche_md_predict(self._h, float(dt), _ptr(pos), _ptr(vel), _ptr(out)))
+        return out
+
+    def learned_guide(self, next_pos):
+        """The learned proposal's guide G at the next positions (arche_learned_guide)."""
+        next_pos = _f64(next_pos, (self.n_atoms, 3))
+        out = np.empty(self.grid)
+        self._check(self._L.arche_learned_guide(self._h, _ptr(next_pos), _ptr(out)))
+        return out
 
     def stress(self, vel=None):
         """(total 3x3 stress tensor, {term: 3x3}) at the last converged solve (Sec. 2.6)."""

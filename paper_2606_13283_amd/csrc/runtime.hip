@@ -411,6 +411,28 @@ arche_status solve_finish(arche_ctx* c, arche_result* out, int fallback) { retur
 arche_status solve_forces(arche_ctx* c) { return do_forces(c); }
 arche_status ctx_error(arche_ctx* c, arche_status s, const std::string& m) { return set_err(c, s, m); }
 
+// Verlet (Sec. 2.1) with the forces of the context's converged solve at r:
+// the start r(-dt) = r - v dt + F dt^2/(2m), and r(t+dt) = 2 r - r(t-dt) + F dt^2/m
+// with the central-difference velocity v(t) = (r(t+dt) - r(t-dt)) / (2 dt).
+void verlet_start(const arche_ctx* c, double dt, const double* r, const double* vel, double* r_prev) {
+  const std::vector<double>& F = c->h_forces;
+  for (int j = 0; j < c->n_atoms; ++j) {
+    const double m = c->mass[c->species[j]];
+    for (int a = 0; a < 3; ++a) r_prev[3 * j + a] = r[3 * j + a] - vel[3 * j + a] * dt + F[3 * j + a] * dt * dt / (2.0 * m);
+  }
+}
+void verlet_next(const arche_ctx* c, double dt, const double* r, const double* r_prev, double* rn, double* v) {
+  const std::vector<double>& F = c->h_forces;
+  for (int j = 0; j < c->n_atoms; ++j) {
+    const double m = c->mass[c->species[j]];
+    for (int a = 0; a < 3; ++a) {
+      const int q = 3 * j + a;
+      rn[q] = 2.0 * r[q] - r_prev[q] + F[q] * dt * dt / m;
+      if (v) v[q] = (rn[q] - r_prev[q]) / (2.0 * dt);
+    }
+  }
+}
+
 namespace {
 std::mutex g_alloc_mtx;
 DevAllocator g_allocator;  // installed by arche_set_allocator (null pair: hipMalloc)
@@ -588,23 +610,12 @@ arche_status arche_md_step(arche_ctx* c, double dt, double* pos_io, double* vel_
   }
   arche_status s = do_forces(c);
   if (s != ARCHE_OK) return s;
-  std::vector<double> r(pos_io, pos_io + 3 * n), F = c->h_forces, rn(3 * n), v(3 * n);
+  std::vector<double> r(pos_io, pos_io + 3 * n), rn(3 * n), v(3 * n);
   if (!c->have_r_prev) {
     c->r_prev.resize(3 * n);
-    for (int j = 0; j < n; ++j) {
-      const double m = c->mass[c->species[j]];
-      for (int a = 0; a < 3; ++a)
-        c->r_prev[3 * j + a] = r[3 * j + a] - vel_io[3 * j + a] * dt + F[3 * j + a] * dt * dt / (2.0 * m);
-    }
+    verlet_start(c, dt, pos_io, vel_io, c->r_prev.data());
   }
-  for (int j = 0; j < n; ++j) {
-    const double m = c->mass[c->species[j]];
-    for (int a = 0; a < 3; ++a) {
-      const int q = 3 * j + a;
-      rn[q] = 2.0 * r[q] - c->r_prev[q] + F[q] * dt * dt / m;
-      v[q] = (rn[q] - c->r_prev[q]) / (2.0 * dt);
-    }
-  }
+  verlet_next(c, dt, pos_io, c->r_prev.data(), rn.data(), v.data());
   s = do_solve(c, rn.data(), out, c->p.init);
   if (s != ARCHE_OK) {
     c->have_r_prev = false;
@@ -758,6 +769,45 @@ arche_status arche_debug_get(arche_ctx* c, int32_t which, double* dst_host) {
 
 arche_status arche_debug_one_center(arche_ctx* c, const double* pos_host, double* n_init_host, int32_t* used_fallback) {
   return arche_debug_one_center2(c, pos_host, n_init_host, used_fallback, nullptr);
+}
+
+arche_status arche_md_predict(arche_ctx* c, double dt, const double* pos_host, const double* vel_host,
+                              double* next_host) {
+  if (!c || !pos_host || !vel_host || !next_host) return set_err(c, ARCHE_EINVAL, "NULL argument");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return set_err(c, ARCHE_EINVAL, "dt must be positive");
+  const int n = c->n_atoms;
+  const bool same = c->solved && c->converged && c->h_pos.size() == (size_t)3 * n &&
+                    std::memcmp(c->h_pos.data(), pos_host, 3 * n * sizeof(double)) == 0;
+  if (!same) return set_err(c, ARCHE_ESTATE, "no converged solve at these positions");
+  arche_status s = do_forces(c);
+  if (s != ARCHE_OK) return s;
+  std::vector<double> rp(3 * n);
+  if (c->have_r_prev)
+    rp = c->r_prev;
+  else
+    verlet_start(c, dt, pos_host, vel_host, rp.data());
+  verlet_next(c, dt, pos_host, rp.data(), next_host, nullptr);
+  return ARCHE_OK;
+}
+
+arche_status arche_learned_guide(arche_ctx* c, const double* next_pos_host, double* guide_host) {
+  if (!c || !next_pos_host || !guide_host) return set_err(c, ARCHE_EINVAL, "NULL argument");
+  if (!c->have_prev || !c->solved || !c->converged) return set_err(c, ARCHE_ESTATE, "no converged previous step");
+  for (int q = 0; q < 3 * c->n_atoms; ++q)
+    if (!std::isfinite(next_pos_host[q])) return set_err(c, ARCHE_EINVAL, "non-finite position");
+  // the ionic field and structure factors of the next positions (recomputed by
+  // the next solve anyway); the converged state, its positions and forces stay
+  CK(hipMemcpyAsync(c->pos, next_pos_host, 3 * c->n_atoms * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  CK(ionic_structure(c));
+  int fb = 0;
+  CK(scf_one_center_density(c, &fb, nullptr, c->lap_a));
+  CK(scf_add_scalar(c, c->lap_a, c->Ne / c->g.vol));
+  CK(hipMemcpyAsync(guide_host, c->lap_a, c->g.ng * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  // the device copy of the positions back to those of the converged solve
+  CK(hipMemcpyAsync(c->pos, c->h_pos.data(), 3 * c->n_atoms * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  CK(ionic_structure(c));
+  CK(hipStreamSynchronize(c->stream));
+  return ARCHE_OK;
 }
 
 arche_status arche_debug_one_center2(arche_ctx* c, const double* pos_host, double* n_init_host, int32_t* used_fallback,

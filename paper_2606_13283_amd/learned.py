@@ -50,38 +50,41 @@ def _dev(a):
 
 
 class Trajectory:
-    """Verlet MD (Sec. 2.1) driven from Python around Context.solve, so that the
-    guess for the next step can be recorded before the solve."""
+    """Verlet MD (Sec. 2.1) through the library (arche_md_step); before a step,
+    the learned proposal's guide at the next positions can be recorded
+    (arche_md_predict, arche_learned_guide), for training samples."""
 
     def __init__(self, w, init=arche.INIT_ONE_CENTER, net=None, tol=1e-10):
         self.w = w
         self.ctx = arche.Context.from_workload(w, _opts(w, init, tol))
         if net is not None:
             self.ctx.set_init_net(net)
-        self.m = np.array([w.mass[s] for s in w.species])[:, None]
-        self.r = w.pos.copy()
-        self.res = self.ctx.solve(self.r)
-        self.F = self.ctx.forces()
-        v = w.vel if w.vel is not None else np.zeros_like(self.r)
-        self.r_prev = self.r - v * w.dt + self.F * w.dt ** 2 / (2 * self.m)
+        self.pos = w.pos.copy()
+        self.vel = (w.vel if w.vel is not None else np.zeros_like(self.pos)).copy()
+        self.res = self.ctx.solve(self.pos)
 
     def next_positions(self):
-        return 2 * self.r - self.r_prev + self.F * self.w.dt ** 2 / self.m
+        return self.ctx.md_predict(self.w.dt, self.pos, self.vel)
 
-    def step(self, r_next=None, record=False):
-        """One step; returns (result, sample or None)."""
-        r_next = self.next_positions() if r_next is None else r_next
+    def step(self, record=False):
+        """One MD step; returns (result, sample or None), the sample being
+        (guide G, previous converged density, converged density) on the device."""
         sample = None
         if record:
             p = self.ctx.density()
-            _, _, g = self.ctx.one_center_raw(r_next)
-        res = self.ctx.solve(r_next)
+            g = self.ctx.learned_guide(self.next_positions())
+        self.pos, self.vel, _, res = self.ctx.md_step(self.w.dt, self.pos, self.vel)
         if record:
             sample = (_dev(g), _dev(p), _dev(self.ctx.density()))
-        self.r_prev, self.r = self.r, r_next
-        self.F = self.ctx.forces()
         self.res = res
         return res, sample
+
+    def solve_at(self, pos):
+        """A solve at given positions (another trajectory's), with this
+        context's initial density."""
+        self.pos = np.array(pos, dtype=np.float64)
+        self.res = self.ctx.solve(self.pos)
+        return self.res
 
     def close(self):
         self.ctx.close()
@@ -128,21 +131,25 @@ def compare(w, net, steps):
     """The plain guess (one-center, uniform where it rings negative), the
     previous converged density alone (what an untrained network proposes) and
     the learned proposal, solved at the same positions: the plain trajectory
-    drives the positions, the others follow it.  Per-step SCF iterations and
-    free energies."""
+    drives the positions, the others follow it, one after another with only
+    their own context alive.  Per-step SCF iterations and free energies."""
+    rows = [dict() for _ in range(steps)]
+    positions = []
     plain = Trajectory(w)
+    for k in range(steps):
+        a, _ = plain.step()
+        positions.append(plain.pos.copy())
+        rows[k].update(plain_iters=a["scf_iters"], plain_fallback=a["used_fallback"], F_plain=a["F"])
+    plain.close()
     prev = Trajectory(w, init=arche.INIT_KEEP)
-    learned = Trajectory(w, init=arche.INIT_LEARNED, net=net)
-    rows = []
-    for _ in range(steps):
-        r_next = plain.next_positions()
-        a, _ = plain.step(r_next)
+    for k in range(steps):
         prev.ctx.set_density(prev.ctx.density())
-        c, _ = prev.step(r_next)
-        b, _ = learned.step(r_next)
-        rows.append({"plain_iters": a["scf_iters"], "plain_fallback": a["used_fallback"],
-                     "prev_iters": c["scf_iters"], "learned_iters": b["scf_iters"], "F_plain": a["F"],
-                     "F_prev": c["F"], "F_learned": b["F"], "fallback": b["used_fallback"]})
-    for t in (plain, prev, learned):
-        t.close()
+        c = prev.solve_at(positions[k])
+        rows[k].update(prev_iters=c["scf_iters"], F_prev=c["F"])
+    prev.close()
+    learned = Trajectory(w, init=arche.INIT_LEARNED, net=net)
+    for k in range(steps):
+        b = learned.solve_at(positions[k])
+        rows[k].update(learned_iters=b["scf_iters"], F_learned=b["F"], fallback=b["used_fallback"])
+    learned.close()
     return rows

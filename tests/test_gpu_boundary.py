@@ -154,3 +154,31 @@ def test_torch_allocator_supplies_context_memory():
         arche.use_torch_allocator(False)
     assert ra["F"] == rb["F"] and ra["scf_iters"] == rb["scf_iters"]
     assert np.array_equal(na, nb)
+
+
+def test_md_predict_and_learned_guide_leave_the_step_unchanged():
+    """arche_md_predict returns the positions arche_md_step then moves to, and
+    arche_learned_guide between them changes nothing of the step (bit-identical
+    to the same step without the calls)."""
+    w = W.small_random(8, 20, 2.7, 5.0, seed=12)
+    vel = np.random.default_rng(5).normal(0, 1e-3, w.pos.shape)
+    out = []
+    for probe in (False, True):
+        ctx = arche.Context.from_workload(w, opts_of(w, init=arche.INIT_ONE_CENTER))
+        pos, v = w.pos.copy(), vel.copy()
+        ctx.solve(pos)
+        steps = []
+        for k in range(3):
+            if probe:
+                nxt = ctx.md_predict(w.dt, pos, v)
+                if k > 0:
+                    G = ctx.learned_guide(nxt)
+                    assert np.all(np.isfinite(G)) and abs(np.mean(G) / (24.0 / np.prod(w.cell)) - 1) < 1e-6
+            pos, v, F, res = ctx.md_step(w.dt, pos, v)
+            if probe:
+                assert np.array_equal(pos, nxt)
+            steps.append((pos.copy(), F.copy(), res["F"], res["scf_iters"]))
+        ctx.close()
+        out.append(steps)
+    for a, b in zip(*out):
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2] == b[2] and a[3] == b[3]

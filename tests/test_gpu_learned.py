@@ -50,20 +50,35 @@ def test_training_converges(trained):
     assert hist[-1] < 0.5 * hist[0]
 
 
-def test_learned_guess_saves_iterations(trained):
+@pytest.fixture(scope="module")
+def compared(trained):
     net, _ = trained
     rows = LN.compare(W.fcc256_at(5.0, seed=300), net, steps=8)
     for r in rows:
         say(r)
-        assert r["fallback"] == 0
-        assert abs(r["F_learned"] - r["F_plain"]) <= 1e-9 * abs(r["F_plain"])
     plain = np.mean([r["plain_iters"] for r in rows])
     prev = np.mean([r["prev_iters"] for r in rows])
     lrn = np.mean([r["learned_iters"] for r in rows])
     say("mean SCF iterations: plain guess %.1f, previous density alone %.1f, learned %.1f" % (plain, prev, lrn))
+    return rows, plain, prev, lrn
+
+
+def test_learned_guess_saves_iterations(compared):
+    rows, plain, prev, lrn = compared
     for r in rows:
+        assert r["fallback"] == 0
+        assert abs(r["F_learned"] - r["F_plain"]) <= 1e-9 * abs(r["F_plain"])
         assert abs(r["F_prev"] - r["F_plain"]) <= 1e-9 * abs(r["F_plain"])
     assert lrn < plain
+
+
+@pytest.mark.xfail(strict=False, reason="trained on 80 samples, the network's proposal does not yet beat its own "
+                                        "input, the previous converged density (175 vs 156 iterations per step)")
+def test_learned_beats_previous_density(compared):
+    """The network's gain over the method without it: fewer iterations than its
+    own input, the previous converged density alone."""
+    rows, plain, prev, lrn = compared
+    assert lrn < prev
 
 
 def test_unusable_proposal_falls_back():
