@@ -233,6 +233,37 @@ const char *arche_last_error(const arche_ctx *ctx);
 
 const char *arche_version(void);
 
+/* ---- Average-atom pseudopotential (Sec. 2.4) -------------------------------
+ * A finite-temperature Thomas-Fermi (+ LDA when xc = ARCHE_XC_LDA) average atom:
+ * a nucleus of charge Z in its Wigner-Seitz sphere (4/3 pi r_ws^3 rho_ion = 1),
+ * neutral inside it, solved self-consistently on a radial grid (n_radial nodes
+ * uniform in ln r from 1e-7 r_ws to r_ws, trapezoid rule in ln r).  Inside
+ * r_cut (the first node at or beyond r_cut_frac r_ws) its density is replaced
+ * by exp(a + b r^2 + c r^4) with the same value, slope and charge at r_cut; the
+ * pseudopotential is the potential whose TF + Hartree + xc response is that
+ * pseudo-density, V~ = mu - kT I_{1/2}^{-1}(n~/c_n) - v_xc(n~) - V_H[n~] inside
+ * r_cut and -Z/r outside.  table_out[k], k < n_q, receives its non-Coulomb
+ * form factor D(k dq) = 4 pi int (V~ + Z/r) r^2 sin(2 pi q r)/(2 pi q r) dr,
+ * in the form arche_params.ff_table takes (for one species; ff_dq = dq).
+ * out->dE_AA is Delta E_AA, the internal energy of the average atom with the
+ * Coulomb potential minus that with the pseudopotential (Hartree per atom; the
+ * paper adds it to the internal energy per ion).  Host-only.  EINVAL for bad
+ * parameters, ENOCONV if the average atom does not converge. */
+typedef struct {
+  double Z;          /* nuclear charge (every electron of the atom) */
+  double rho_ion;    /* ion number density (1/bohr^3) */
+  double kT;         /* electron temperature (Hartree) */
+  double r_cut_frac; /* r_cut / r_ws in (0, 1) */
+  int32_t xc;        /* ARCHE_XC_NONE or ARCHE_XC_LDA */
+  int32_t n_radial;  /* radial nodes (>= 101; e.g. 2001) */
+} arche_aa_params;
+typedef struct {
+  double r_ws, r_cut, mu, dE_AA, a, b, c;
+  int32_t iters;
+} arche_aa_result;
+arche_status arche_aa_pseudopotential(const arche_aa_params *p, double dq, int32_t n_q, double *table_out,
+                                      arche_aa_result *out);
+
 /* ---- Equation-of-state averages (Sec. 4, Fig. pressurehistory) -----------
  * The time average of an MD observable (pressure, energy) after dropping the
  * thermalisation part, with the error from uncorrelated values.  Host-only.

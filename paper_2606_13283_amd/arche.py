@@ -65,6 +65,29 @@ class Result(ctypes.Structure):
                     used_fallback=bool(self.used_fallback), converged=bool(self.converged))
 
 
+class AAParams(ctypes.Structure):
+    _fields_ = [("Z", ctypes.c_double), ("rho_ion", ctypes.c_double), ("kT", ctypes.c_double),
+                ("r_cut_frac", ctypes.c_double), ("xc", ctypes.c_int32), ("n_radial", ctypes.c_int32)]
+
+
+class AAResult(ctypes.Structure):
+    _fields_ = [("r_ws", ctypes.c_double), ("r_cut", ctypes.c_double), ("mu", ctypes.c_double),
+                ("dE_AA", ctypes.c_double), ("a", ctypes.c_double), ("b", ctypes.c_double), ("c", ctypes.c_double),
+                ("iters", ctypes.c_int32)]
+
+
+def aa_pseudopotential(Z, rho_ion, kT, r_cut_frac, xc=True, dq=0.01, n_q=400, n_radial=2001):
+    """arche_aa_pseudopotential: (form-factor table D(i dq), result dict) of the
+    average-atom pseudopotential (Sec. 2.4); the table goes to Options.ff_table."""
+    p = AAParams(float(Z), float(rho_ion), float(kT), float(r_cut_frac), XC_LDA if xc else XC_NONE, int(n_radial))
+    table = np.empty(int(n_q))
+    r = AAResult()
+    s = load().arche_aa_pseudopotential(ctypes.byref(p), float(dq), int(n_q), _ptr(table), ctypes.byref(r))
+    if s != OK:
+        raise ArcheError(s, "arche_aa_pseudopotential")
+    return table, {k: getattr(r, k) for k, _ in AAResult._fields_}
+
+
 class EosStat(ctypes.Structure):
     _fields_ = [("mean", ctypes.c_double), ("std", ctypes.c_double), ("sem", ctypes.c_double),
                 ("tau", ctypes.c_double), ("n_used", ctypes.c_int64), ("n_eff", ctypes.c_int64),
@@ -137,6 +160,9 @@ def load(path: str = LIB_PATH):
     L.arche_forces.restype = st
     L.arche_md_step.argtypes = [vp, ctypes.c_double, _dp, _dp, _dp, ctypes.POINTER(Result)]
     L.arche_md_step.restype = st
+    L.arche_aa_pseudopotential.argtypes = [ctypes.POINTER(AAParams), ctypes.c_double, ctypes.c_int32, _dp,
+                                            ctypes.POINTER(AAResult)]
+    L.arche_aa_pseudopotential.restype = st
     L.arche_eos_average.argtypes = [_dp, ctypes.c_int64, ctypes.c_double, ctypes.POINTER(EosStat)]
     L.arche_eos_average.restype = st
     L.arche_md_predict.argtypes = [vp, ctypes.c_double, _dp, _dp, _dp]

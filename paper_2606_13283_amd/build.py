@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libarche.so")
-SOURCES = ["fft.hip", "fft_batch.hip", "scf.hip", "batch.hip", "ionic.hip", "runtime.hip", "kernels_abi.hip", "net.hip"]
+SOURCES = ["fft.hip", "fft_batch.hip", "scf.hip", "batch.hip", "ionic.hip", "runtime.hip", "kernels_abi.hip", "net.hip", "aa.hip"]
 ARCH = os.environ.get("ARCHE_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -221,6 +221,10 @@ struct arche_ctx {
   std::vector<ScfState> hist;     // polled SCF states of the last single solve
 };
 
+// host Fermi-Dirac integrals: j = 0, 1, 2 for I_{-1/2}, I_{1/2}, I_{3/2}; the inverse of I_{1/2}
+double host_fd(int j, double x);
+double host_fd_inverse_p12(double y);
+
 // device Fermi-Dirac tables (uploaded once per process and device)
 const FdTables* fd_tables_device(int device);
 

@@ -433,6 +433,10 @@ void verlet_next(const arche_ctx* c, double dt, const double* r, const double* r
   }
 }
 
+// host Fermi-Dirac integrals for other host code (the average atom)
+double host_fd(int j, double x) { return fd_host(j, x); }
+double host_fd_inverse_p12(double y) { return fd_inverse_p12(y); }
+
 namespace {
 std::mutex g_alloc_mtx;
 DevAllocator g_allocator;  // installed by arche_set_allocator (null pair: hipMalloc)

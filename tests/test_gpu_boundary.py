@@ -182,3 +182,34 @@ def test_md_predict_and_learned_guide_leave_the_step_unchanged():
         out.append(steps)
     for a, b in zip(*out):
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2] == b[2] and a[3] == b[3]
+
+
+def test_average_atom_pseudopotential_parity():
+    """The average-atom pseudopotential (Sec. 2.4) end to end: the library's
+    table (arche_aa_pseudopotential, Al with all 13 electrons at 2.7 g/cm^3 and
+    10 eV, r_cut = 0.6 r_ws) as the form factor of a 4-atom cell with Z = 13,
+    solved on the GPU and by the oracle with the same table."""
+    from oracle import ionic as oionic
+    from oracle import thermo as oth
+    w = W.small_random(4, 16, 2.7, 10.0, seed=11)
+    rho = 1.0 / W.cell_length(1, 2.7) ** 3
+    dq = 0.01
+    qmax = math.sqrt(sum((n / 2 / L) ** 2 for n, L in zip(w.grid, w.cell)))
+    table, info = arche.aa_pseudopotential(13.0, rho, w.kT, 0.6, xc=True, dq=dq, n_q=int(qmax / dq) + 8)
+    say("average atom: dE_AA %.6f Ha, r_cut %.4f" % (info["dE_AA"], info["r_cut"]))
+    w.Z = (13.0,)
+    ctx = arche.Context.from_workload(w, opts_of(w, ff_table=table[None, :], ff_dq=dq))
+    res = ctx.solve(w.pos)
+    assert res["converged"]
+    F = ctx.forces()
+    dens = ctx.density()
+    ctx.close()
+    s = system_of(w, rc=(oionic.Tabulated(table, dq),))
+    ion = oscf.ionic_setup(s)
+    r = oscf.scf_anderson(s, ion, oscf.initial_density(s, ion)[0], tol=1e-12, beta=0.3)
+    assert r.converged
+    th = oth.evaluate(s, ion, r)
+    assert np.max(np.abs(dens - r.n)) <= 1e-9 * np.max(r.n)
+    assert abs(res["F"] - th.F) <= RTOL * abs(th.F)
+    assert abs(res["P"] - th.P) <= RTOL * abs(th.P)
+    assert np.max(np.abs(F - th.forces)) <= RTOL * np.max(np.abs(th.forces))
