@@ -32,10 +32,11 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6  # vector FP64: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
-# algorithmic FP64 flops per grid point of the SCF kernel: one Fermi-Dirac
-# evaluation pass (I_{1/2} with its derivative and the sums) ~130, the
-# potential assembly with LDA xc ~60; the kernel makes 1 + m passes, m the
-# Newton passes that confirm mu
+# algorithmic FP64 flops per grid point of the SCF kernel: each evaluation of
+# N(mu) (I_{1/2} with its derivatives and the sums) ~130, the potential
+# assembly with LDA xc ~60; the kernel makes m evaluations (the one at the
+# previous mu during the assembly, then Newton's, the last of which forms the
+# active density)
 FLOP_PER_FD_PASS = 130.0
 FLOP_ASSEMBLY_XC = 60.0
 # algorithmic HBM bytes per grid point of one whole SCF iteration (every pass
@@ -261,7 +262,9 @@ def bench_ablation(steps):
 
     w = W.fcc256()
     setups = {"A": (arche.INIT_UNIFORM, arche.MIX_FIXED), "B": (arche.INIT_UNIFORM, arche.MIX_MORE),
-              "C": (arche.INIT_ONE_CENTER, arche.MIX_FIXED), "D": (arche.INIT_ONE_CENTER, arche.MIX_MORE)}
+              "C": (arche.INIT_ONE_CENTER, arche.MIX_FIXED), "D": (arche.INIT_ONE_CENTER, arche.MIX_MORE),
+              # B with More's weight exactly as printed (Hartree-only U, second-order K)
+              "B_printed": (arche.INIT_UNIFORM, arche.MIX_MORE_PRINTED)}
     ctx = {}
     for k, (init, mix) in setups.items():
         o = arche.Options(w_fixed=w.w_fixed, lambda_vw=w.lam, xc=arche.XC_LDA, init=init, mixing=mix,
@@ -273,16 +276,16 @@ def bench_ablation(steps):
     fallback = {k: [] for k in setups}
     spread = []
     t0 = time.perf_counter()
-    res = {k: c.solve(r) for k, c in ctx.items()}
+    res = {k: c.solve(r, allow_noconv=True) for k, c in ctx.items()}
     F = ctx["D"].forces()
     r_prev = r - w.vel * w.dt + F * w.dt ** 2 / (2 * m)
     for step in range(steps):
         r_next = 2 * r - r_prev + F * w.dt ** 2 / m
-        res = {k: c.solve(r_next) for k, c in ctx.items()}
+        res = {k: c.solve(r_next, allow_noconv=True) for k, c in ctx.items()}
         for k in setups:
-            iters[k].append(res[k]["scf_iters"])
+            iters[k].append(res[k]["scf_iters"] if res[k]["converged"] else None)
             fallback[k].append(int(res[k]["used_fallback"]))
-        Fs = [res[k]["F"] for k in setups]
+        Fs = [res[k]["F"] for k in setups if res[k]["converged"]]
         spread.append((max(Fs) - min(Fs)) / abs(res["D"]["F"]))
         F = ctx["D"].forces()
         r_prev, r = r, r_next
@@ -290,9 +293,43 @@ def bench_ablation(steps):
     for c in ctx.values():
         c.close()
     return {"workload": w.name, "md_steps": steps, "scf_tol": 1e-10,
-            "total_scf_iters": {k: int(sum(v)) for k, v in iters.items()},
+            "total_scf_iters": {k: (int(sum(v)) if None not in v else None) for k, v in iters.items()},
+            "not_converged_steps": {k: sum(x is None for x in v) for k, v in iters.items()},
             "scf_iters_each_step": iters, "one_center_fallback_each_step": {"C": fallback["C"], "D": fallback["D"]},
             "max_rel_F_spread": max(spread) if spread else None, "seconds": time.perf_counter() - t0}
+
+
+def bench_large(w_name="rand4000"):
+    """The 4000-atom cell at 192^3 and 10 eV: one SCF from the uniform density
+    (then one more, timed), forces and stress; SCF iterations/s and grid-point
+    updates/s of the single-snapshot solve at the largest configured grid."""
+    import torch
+
+    from paper_2606_13283_amd import arche
+    from paper_2606_13283_amd import workloads as W
+
+    w = getattr(W, w_name)()
+    o = arche.Options(w_fixed=w.w_fixed, init=arche.INIT_UNIFORM, scf_tol=1e-10, exclusive_device=1)
+    ctx = arche.Context.from_workload(w, o)
+    r0 = ctx.solve(w.pos)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = ctx.solve(w.pos)
+    t_solve = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ctx.forces()
+    t_forces = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ctx.stress()
+    t_stress = time.perf_counter() - t0
+    ctx.close()
+    ng = w.grid[0] * w.grid[1] * w.grid[2]
+    print("[bench] large: %s %d SCF iterations in %.3f s" % (w.name, r["scf_iters"], t_solve), file=sys.stderr,
+          flush=True)
+    return {"workload": w.name, "n_atoms": int(w.pos.shape[0]), "grid": list(w.grid), "scf_iters": r["scf_iters"],
+            "solve_s": t_solve, "scf_iters_per_s": r["scf_iters"] / t_solve,
+            "grid_point_updates_per_s": ng * r["scf_iters"] / t_solve, "forces_s": t_forces, "stress_s": t_stress,
+            "F": r["F"], "P": r["P"], "first_solve_same_F": r0["F"] == r["F"]}
 
 
 def main():
@@ -305,7 +342,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--batch", type=int, default=64, help="snapshots of the batched-solve comparison (0: skip)")
     ap.add_argument("--learned", type=int, default=8, help="MD steps of the learned-init comparison (0: skip)")
-    ap.add_argument("--ablation", type=int, default=0,
+    ap.add_argument("--large", type=int, default=1, help="1: time one SCF of the 4000-atom 192^3 cell (0: skip)")
+    ap.add_argument("--ablation", type=int, default=6,
                     help="MD steps of the A/B/C/D SCF-count ablation on the 256-atom cell (0: skip)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device 5 times (calibrates the HBM byte counters)")
@@ -417,11 +455,11 @@ def main():
     traffic = traffic_for(dom)
     # the SCF kernel is bound by FP64 arithmetic (Fermi-Dirac evaluations), not
     # HBM: price it against the FP64 vector peak with its algorithmic flops
-    flops = ng * (FLOP_PER_FD_PASS * (1.0 + newton_per_launch) + FLOP_ASSEMBLY_XC)
+    flops = ng * (FLOP_PER_FD_PASS * newton_per_launch + FLOP_ASSEMBLY_XC)
     tflops = flops / (d["avg_us"] * 1e-6) / 1e12
     roofline = {"bound": "alu", "kernel": dom, "achieved": tflops, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": tflops / PEAK_FP64_TFLOPS, "traffic": traffic,
-                "alg_flops_per_launch": flops, "newton_passes_per_launch": newton_per_launch,
+                "alg_flops_per_launch": flops, "mu_evaluations_per_launch": newton_per_launch,
                 "counter_fp64_flops_per_launch": counter_flops_for(dom),
                 "alg_bytes_per_launch": d["alg_bytes_per_launch"], "hbm_GBps": d["GBps"],
                 "hbm_frac": d["GBps"] / PEAK_HBM_GBS, "avg_launch_us": d["avg_us"]}
@@ -465,6 +503,8 @@ def main():
         out["learned_init"] = bench_learned(16, 12, args.learned)
     if args.ablation > 0:
         out["ablation"] = bench_ablation(args.ablation)
+    if args.large > 0:
+        out["large_snapshot"] = bench_large()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out))
