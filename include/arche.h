@@ -198,7 +198,7 @@ arche_status arche_stress(arche_ctx *ctx, const double *vel_host, double *sigma_
 arche_status arche_md_predict(arche_ctx *ctx, double dt, const double *pos_host, const double *vel_host,
                               double *next_host);
 
-/* Copy the converged density n_a/* Copy the converged density n_a [Nx][Ny][Nz] to dst (host if
+/* Copy the converged density n_a [Nx][Ny][Nz] to dst (host if
  * dst_on_device == 0, else device memory on the context's device).  ESTATE
  * before a solve. */
 arche_status arche_get_density(arche_ctx *ctx, double *dst, int32_t dst_on_device);
@@ -281,7 +281,7 @@ typedef struct {
 } arche_eos_stat;
 arche_status arche_eos_average(const double *series, int64_t n, double thermal_fraction, arche_eos_stat *out);
 
-/* ---- Batched solves:/* ---- Batched solves: many independent snapshots on one GPU ----------------
+/* ---- Batched solves: many independent snapshots on one GPU ----------------
  * A batch holds one context per snapshot (each its own cell, grid, atoms,
  * temperature and SCF options) on one stream.  arche_batch_solve runs the SCF
  * of every snapshot together: each pass of an iteration is ONE launch over all

@@ -192,6 +192,8 @@ def load(path: str = LIB_PATH):
     L.arche_profile_enable.argtypes = [vp, ctypes.c_int32]
     L.arche_profile_enable.restype = st
     L.arche_profile_reset.argtypes = [vp]
+    L.arche_profile_sample.argtypes = [vp, ctypes.c_int32]
+    L.arche_profile_sample.restype = st
     L.arche_profile_reset.restype = st
     L.arche_profile_read.argtypes = [vp, ctypes.c_int32, _dp, ctypes.POINTER(ctypes.c_int64)]
     L.arche_profile_read.restype = st
@@ -464,6 +466,10 @@ class Context:
         else:
             code = sum(2 << PROF_NAMES.index(k) for k in kinds)
         self._check(self._L.arche_profile_enable(self._h, code))
+
+    def profile_sample(self, every):
+        """Time one launch in `every` of each kind."""
+        self._check(self._L.arche_profile_sample(self._h, int(every)))
 
     def profile_reset(self):
         self._check(self._L.arche_profile_reset(self._h))

@@ -88,7 +88,7 @@ struct ActiveArgs {
   ScfState* st;
   double* part;     // [13][nchunk] chunk partials
   double* res;      // reduced scalars
-  unsigned* flags;  // [G] arrival flags of the group, then the go word
+  unsigned* flags;  // two banks of ARRIVE_LANES arrival counters (grid_allreduce)
   int* err;
   const FdTables* fdt;
   int64_t ng, nchunk;
@@ -149,6 +149,8 @@ struct IterStep {
 
 // SCF iterations per graph launch of a single-context solve, and the host ring
 // that holds the states of two launches (the host reads one launch behind)
+// words of a context's grid all-reduce counters: two banks (grid_allreduce)
+constexpr int SCF_BAR_WORDS = 2 * (int)ARRIVE_BANK;
 constexpr int ARCHE_GRAPH_ITERS = 4;
 constexpr int ARCHE_RING = 2 * ARCHE_GRAPH_ITERS;
 
@@ -188,6 +190,7 @@ struct arche_ctx {
   int32_t *spec_d = nullptr, *sp_order = nullptr, *sp_begin = nullptr;
   cplx *Wp = nullptr, *Wm = nullptr;  // force weights per species [ns][nh]
   cplx *phx = nullptr, *phy = nullptr, *phz = nullptr;  // [n_atoms][N] phase tables
+  cplx* phT = nullptr;  // the phase tables transposed, atoms in species order [N_x + N_y + N_h][n_atoms]
   // reductions
   double *partials = nullptr;  // scratch for block partials
   int partial_cap = 0;
@@ -199,7 +202,7 @@ struct arche_ctx {
   hipGraphExec_t iter_exec = nullptr;
   bool graph_tried = false;
   bool graph_plain = false;  // the captured SCF kernel launch is a plain one
-  unsigned *bar = nullptr;         // grid all-reduce arrival flags [coop_blocks] + go word
+  unsigned *bar = nullptr;         // grid all-reduce arrival counters [scf_bar_words]
   int *err_d = nullptr;
   const FdTables *fdt = nullptr;
 

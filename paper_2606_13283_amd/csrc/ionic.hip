@@ -28,13 +28,14 @@ __device__ inline void half_index(int64_t m, int Ny, int Nh, int& ix, int& iy, i
 
 __device__ inline int box_m(int i, int N) { return i <= N / 2 ? i : i - N; }
 
-// phase tables exp(-2 pi i k_m x / L) for atom j and box index m (axis a), z only m <= Nz/2
+// phase tables exp(-2 pi i k_m x / L) for box index m (axis a), z only m <= Nz/2,
+// one row per atom in species order: row q holds atom order[q]
 __global__ void __launch_bounds__(ARCHE_BLOCK)
-k_phases(const double* pos, int n_atoms, GridInfo g, cplx* phx, cplx* phy, cplx* phz) {
+k_phases(const double* pos, const int* __restrict__ order, int n_atoms, GridInfo g, cplx* phx, cplx* phy, cplx* phz) {
   const int64_t total = (int64_t)n_atoms * (g.N[0] + g.N[1] + g.Nh);
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
-    int64_t j = q / (g.N[0] + g.N[1] + g.Nh);
-    int r = (int)(q - j * (g.N[0] + g.N[1] + g.Nh));
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t q = e / (g.N[0] + g.N[1] + g.Nh);
+    int r = (int)(e - q * (g.N[0] + g.N[1] + g.Nh));
     int axis, i;
     if (r < g.N[0]) {
       axis = 0;
@@ -46,6 +47,7 @@ k_phases(const double* pos, int n_atoms, GridInfo g, cplx* phx, cplx* phy, cplx*
       axis = 2;
       i = r - g.N[0] - g.N[1];
     }
+    const int64_t j = order[q];
     const int m = axis == 2 ? i : box_m(i, g.N[axis]);
     double f = pos[j * 3 + axis] / g.L[axis];
     f -= floor(f);
@@ -55,41 +57,143 @@ k_phases(const double* pos, int n_atoms, GridInfo g, cplx* phx, cplx* phy, cplx*
     sincospi(2.0 * th, &s, &c);
     cplx v{c, -s};
     if (axis == 0)
-      phx[j * g.N[0] + i] = v;
+      phx[q * g.N[0] + i] = v;
     else if (axis == 1)
-      phy[j * g.N[1] + i] = v;
+      phy[q * g.N[1] + i] = v;
     else
-      phz[j * g.Nh + i] = v;
+      phz[q * g.Nh + i] = v;
   }
 }
 
-// S+_s(m) = sum_{j in s} P_j(k_m), S-_s(m) = sum_{j in s} P_j(k~_m), atoms sorted by species
-__global__ void __launch_bounds__(ARCHE_BLOCK)
-k_structure(const cplx* __restrict__ phx, const cplx* __restrict__ phy, const cplx* __restrict__ phz,
-            const int* __restrict__ order, const int* __restrict__ sp_begin, int ns, GridInfo g, cplx* Sp, cplx* Sm) {
-  for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < g.nh; m += (int64_t)gridDim.x * blockDim.x) {
-    int ix, iy, iz;
-    half_index(m, g.N[1], g.Nh, ix, iy, iz);
-    const bool nx = 2 * ix == g.N[0], ny = 2 * iy == g.N[1], nz = 2 * iz == g.N[2];
-    const bool nyq = nx || ny || nz;
-    for (int s = 0; s < ns; ++s) {
-      cplx ap{0.0, 0.0}, am{0.0, 0.0};
-      for (int q = sp_begin[s]; q < sp_begin[s + 1]; ++q) {
-        const int j = order[q];
-        cplx a{1.0, 0.0}, b{1.0, 0.0};
-        const cplx px = phx[(int64_t)j * g.N[0] + ix];
-        const cplx py = phy[(int64_t)j * g.N[1] + iy];
-        const cplx pz = phz[(int64_t)j * g.Nh + iz];
-        if (nx) b = px; else a = px;
-        if (ny) b = cmul(b, py); else a = cmul(a, py);
-        if (nz) b = cmul(b, pz); else a = cmul(a, pz);
-        ap = cadd(ap, cmul(a, b));
-        if (nyq) am = cadd(am, cmul(a, cconj(b)));
+// S+_s(m) = sum_{j in s} P_j(k_m), S-_s(m) = sum_{j in s} P_j(k~_m), atoms
+// sorted by species.  P_j = px py pz splits into the factors without a Nyquist
+// index (a) and those with one (b); S+ sums a b = P, S- sums a conj(b).  The
+// half box is walked as rows (ix, iy) by z indices: each lane takes one row and
+// SZ_CZ consecutive z indices from iz0 = SZ_CZ blockIdx.y.  Atoms go in
+// batches of SZ_AB: the batch's z phases are staged in LDS (read by the whole
+// wave at one address), its row phases per lane in registers, and the next
+// batch's loads are in flight while one is summed.
+//   MIRROR = false: every row; S+ everywhere, and S- where it differs from S+
+//     only by the z Nyquist index (iz = N_z/2: S- sums px py conj(pz)) on rows
+//     without a Nyquist x or y index, S- = S+ elsewhere on those rows.
+//   MIRROR = true: the rows with a Nyquist x or y index (ix = N_x/2 for even
+//     N_x: rows 0..N_y-1 of this launch; iy = N_y/2 for even N_y: the others,
+//     each row once); S- with those row factors conjugated.
+constexpr int SZ_CZ = 8;
+constexpr int SZ_AB = 8;
+__device__ inline void nyq_row_of(int r, const GridInfo& g, int& ix, int& iy) {
+  const int nrx = (g.N[0] % 2 == 0) ? g.N[1] : 0;
+  if (r < nrx) {
+    ix = g.N[0] / 2;
+    iy = r;
+  } else {
+    const int r2 = r - nrx;
+    iy = g.N[1] / 2;
+    ix = (g.N[0] % 2 == 0 && r2 >= g.N[0] / 2) ? r2 + 1 : r2;
+  }
+}
+template <bool MIRROR>
+__device__ inline void structure_rows_body(const cplx* __restrict__ phx, const cplx* __restrict__ phy,
+                                           const cplx* __restrict__ phz, const int* __restrict__ sp_begin, int ns,
+                                           const GridInfo& g, int rows, unsigned bx, cplx* __restrict__ Sp,
+                                           cplx* __restrict__ Sm, cplx (*zl)[SZ_AB * SZ_CZ]) {
+  const int lane = threadIdx.x;
+  const int row = (int)bx * 64 + lane;
+  const int iz0 = (int)blockIdx.y * SZ_CZ;
+  const bool live = row < rows;
+  const int rr = live ? row : rows - 1;
+  int ix, iy;
+  if (MIRROR) {
+    nyq_row_of(rr, g, ix, iy);
+  } else {
+    ix = rr / g.N[1];
+    iy = rr - ix * g.N[1];
+  }
+  const bool nx = 2 * ix == g.N[0], ny = 2 * iy == g.N[1];
+  const bool nyq_row = nx || ny;
+  // the z Nyquist index inside this chunk (uniform), else -1
+  const int tN = (g.N[2] % 2 == 0 && g.N[2] / 2 >= iz0 && g.N[2] / 2 < iz0 + SZ_CZ) ? g.N[2] / 2 - iz0 : -1;
+  for (int s = 0; s < ns; ++s) {
+    cplx acc[SZ_CZ], accN{0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < SZ_CZ; ++t) acc[t] = cplx{0.0, 0.0};
+    const int qb = sp_begin[s], qe = sp_begin[s + 1];
+    // loads of the batch at q0 (atoms past qe clamp to qe - 1; their terms are skipped)
+    cplx xn[SZ_AB], yn[SZ_AB], zn;
+    auto fetch = [&](int q0) {
+#pragma unroll
+      for (int u = 0; u < SZ_AB; ++u) {
+        const int64_t q = min(q0 + u, qe - 1);
+        xn[u] = phx[q * g.N[0] + ix];
+        yn[u] = phy[q * g.N[1] + iy];
       }
-      Sp[(int64_t)s * g.nh + m] = ap;
-      Sm[(int64_t)s * g.nh + m] = nyq ? am : ap;
+      const int64_t q = min(q0 + lane / SZ_CZ, qe - 1);
+      zn = phz[q * g.Nh + min(iz0 + lane % SZ_CZ, g.Nh - 1)];
+    };
+    static_assert(SZ_AB * SZ_CZ == 64, "one z phase per lane");
+    if (qb < qe) fetch(qb);
+    int buf = 0;
+    for (int q0 = qb; q0 < qe; q0 += SZ_AB, buf ^= 1) {
+      zl[buf][lane] = zn;
+      cplx xc[SZ_AB], yc[SZ_AB];
+#pragma unroll
+      for (int u = 0; u < SZ_AB; ++u) {
+        xc[u] = MIRROR && nx ? cconj(xn[u]) : xn[u];
+        yc[u] = MIRROR && ny ? cconj(yn[u]) : yn[u];
+      }
+      __syncthreads();
+      if (q0 + SZ_AB < qe) fetch(q0 + SZ_AB);
+      const int nu = min(SZ_AB, qe - q0);
+#pragma unroll
+      for (int u = 0; u < SZ_AB; ++u) {
+        if (u < nu) {
+          const cplx pxy = cmul(xc[u], yc[u]);
+          const cplx* z = zl[buf] + u * SZ_CZ;
+#pragma unroll
+          for (int t = 0; t < SZ_CZ; ++t) {
+            const cplx zt = z[t];
+            acc[t].x = fma(pxy.x, zt.x, fma(-pxy.y, zt.y, acc[t].x));
+            acc[t].y = fma(pxy.x, zt.y, fma(pxy.y, zt.x, acc[t].y));
+          }
+          if (tN >= 0) {  // pxy conj(pz) at the z Nyquist index
+            const cplx zt = z[tN];
+            accN.x = fma(pxy.x, zt.x, fma(pxy.y, zt.y, accN.x));
+            accN.y = fma(-pxy.x, zt.y, fma(pxy.y, zt.x, accN.y));
+          }
+        }
+        // keeps the compiler from hoisting the next atoms' LDS reads (registers)
+        asm volatile("" ::: "memory");
+      }
+    }
+    __syncthreads();  // the next species reuses the buffers
+    if (live) {
+      const int64_t m0 = ((int64_t)ix * g.N[1] + iy) * g.Nh;
+      cplx* sp = Sp + (int64_t)s * g.nh + m0;
+      cplx* sm = Sm + (int64_t)s * g.nh + m0;
+#pragma unroll
+      for (int t = 0; t < SZ_CZ; ++t) {
+        const int iz = iz0 + t;
+        if (iz < g.Nh) {
+          if (!MIRROR) sp[iz] = acc[t];
+          if (MIRROR == nyq_row && t != tN) sm[iz] = acc[t];
+        }
+      }
+      if (MIRROR == nyq_row && tN >= 0) sm[iz0 + tN] = accN;
     }
   }
+}
+
+// One launch: blocks [0, main_blocks) walk every row (MIRROR = false), the
+// others the rows with a Nyquist x or y index (MIRROR = true), concurrently.
+__global__ void __launch_bounds__(64)
+k_structure_rows(const cplx* __restrict__ phx, const cplx* __restrict__ phy, const cplx* __restrict__ phz,
+                 const int* __restrict__ sp_begin, int ns, GridInfo g, unsigned main_blocks, int nyq_rows,
+                 cplx* __restrict__ Sp, cplx* __restrict__ Sm) {
+  __shared__ cplx zl[2][SZ_AB * SZ_CZ];
+  if (blockIdx.x < main_blocks)
+    structure_rows_body<false>(phx, phy, phz, sp_begin, ns, g, g.N[0] * g.N[1], blockIdx.x, Sp, Sm, zl);
+  else
+    structure_rows_body<true>(phx, phy, phz, sp_begin, ns, g, nyq_rows, blockIdx.x - main_blocks, Sp, Sm, zl);
 }
 
 __device__ inline void kvec(int ix, int iy, int iz, const GridInfo& g, double k[3]) {
@@ -161,15 +265,17 @@ k_vie_hat(const cplx* Sp, const cplx* Sm, SpeciesInfo sp, GridInfo g, cplx* SZp,
   }
 }
 
-// Ewald real-space pairs (minimum image): per-atom forces and half the pair energy
+// Ewald real-space pairs (minimum image): per-atom forces and half the pair
+// energy.  One block per atom j; its threads take the partners l in a fixed
+// stride and the block sums them in a fixed order.
 __global__ void __launch_bounds__(ARCHE_BLOCK)
 k_ewald_pairs(const double* pos, const double* Zat, int n, GridInfo g, double alpha, double* F, double* Uj) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
+  __shared__ double sh[(ARCHE_BLOCK / 64) * 4];
+  const int j = blockIdx.x;
   const double xj = pos[3 * j], yj = pos[3 * j + 1], zj = pos[3 * j + 2];
-  double fx = 0, fy = 0, fz = 0, u = 0;
+  double acc[4] = {0, 0, 0, 0};  // fx, fy, fz, u
   const double c2 = 2.0 * alpha / sqrt(PI);
-  for (int l = 0; l < n; ++l) {
+  for (int l = threadIdx.x; l < n; l += blockDim.x) {
     if (l == j) continue;
     double d[3] = {xj - pos[3 * l], yj - pos[3 * l + 1], zj - pos[3 * l + 2]};
     for (int a = 0; a < 3; ++a) d[a] -= g.L[a] * rint(d[a] / g.L[a]);
@@ -177,16 +283,19 @@ k_ewald_pairs(const double* pos, const double* Zat, int n, GridInfo g, double al
     const double r = sqrt(r2);
     const double zz = Zat[j] * Zat[l];
     const double e = erfc(alpha * r) / r;
-    u += 0.5 * zz * e;
+    acc[3] += 0.5 * zz * e;
     const double coef = zz * (e + c2 * exp(-alpha * alpha * r2)) / r2;
-    fx += coef * d[0];
-    fy += coef * d[1];
-    fz += coef * d[2];
+    acc[0] += coef * d[0];
+    acc[1] += coef * d[1];
+    acc[2] += coef * d[2];
   }
-  F[3 * j] = fx;
-  F[3 * j + 1] = fy;
-  F[3 * j + 2] = fz;
-  Uj[j] = u;
+  block_reduce_n<4>(acc, 0u, sh);
+  if (threadIdx.x == 0) {
+    F[3 * j] = acc[0];
+    F[3 * j + 1] = acc[1];
+    F[3 * j + 2] = acc[2];
+    Uj[j] = acc[3];
+  }
 }
 
 // full-box sum of V_alpha |S_Z|^2 (k != 0)
@@ -241,74 +350,204 @@ k_force_weights(const cplx* nhat, const cplx* SZp, const cplx* SZm, SpeciesInfo 
   }
 }
 
-// F_j = -(2 pi/|Omega|) sum over the full box of Im(W(k) exp(-2 pi i k.r_j)) k, as
-// partial sums over chunks of the half box for a tile of ATILE atoms.
-constexpr int ATILE = 8;
-constexpr int MCHUNK = ARCHE_BLOCK * 16;
-
+// Phase tables transposed for the force kernel: phT = [x: N_x][y: N_y][z: N_h]
+// rows of n_atoms values in species order (the order of the phase tables), so
+// that lanes taking consecutive atoms read consecutive values.
 __global__ void __launch_bounds__(ARCHE_BLOCK)
-k_force_contract(const cplx* __restrict__ Wp, const cplx* __restrict__ Wm, const cplx* __restrict__ phx,
-                 const cplx* __restrict__ phy, const cplx* __restrict__ phz, const int* __restrict__ spec, int n_atoms,
-                 GridInfo g, double* part /*[nchunk][n_atoms][3]*/) {
-  __shared__ double sh[ARCHE_BLOCK / 64];
-  const int tile = blockIdx.y;
-  const int chunk = blockIdx.x;
-  const int j0 = tile * ATILE;
-  const int nj = min(ATILE, n_atoms - j0);
-  double acc[ATILE][3];
-  for (int t = 0; t < ATILE; ++t) acc[t][0] = acc[t][1] = acc[t][2] = 0.0;
-  const int64_t mend = min((int64_t)(chunk + 1) * MCHUNK, g.nh);
-  for (int64_t m = (int64_t)chunk * MCHUNK + threadIdx.x; m < mend; m += blockDim.x) {
-    int ix, iy, iz;
-    half_index(m, g.N[1], g.Nh, ix, iy, iz);
-    double k[3];
-    kvec(ix, iy, iz, g, k);
-    const bool nx = 2 * ix == g.N[0], ny = 2 * iy == g.N[1];
-    const bool interior = iz != 0 && 2 * iz != g.N[2];
-    const bool mirror_differs = interior && (nx || ny);
-    const double wgt = (interior && !mirror_differs) ? 2.0 : 1.0;
-    const double kt[3] = {nx ? -k[0] : k[0], ny ? -k[1] : k[1], k[2]};
-#pragma unroll
-    for (int t = 0; t < ATILE; ++t) {
-      if (t >= nj) break;
-      const int j = j0 + t;
-      const int s = spec[j];
-      const cplx px = phx[(int64_t)j * g.N[0] + ix];
-      const cplx py = phy[(int64_t)j * g.N[1] + iy];
-      const cplx pz = phz[(int64_t)j * g.Nh + iz];
-      const cplx wp = Wp[(int64_t)s * g.nh + m];
-      const cplx P = cmul(cmul(px, py), pz);
-      const double im = wgt * (wp.x * P.y + wp.y * P.x);
-      acc[t][0] += im * k[0];
-      acc[t][1] += im * k[1];
-      acc[t][2] += im * k[2];
-      if (mirror_differs) {
-        const cplx wm = Wm[(int64_t)s * g.nh + m];
-        const cplx Pt = cmul(cmul(nx ? cconj(px) : px, ny ? cconj(py) : py), pz);
-        const double im2 = wm.x * Pt.y + wm.y * Pt.x;
-        acc[t][0] += im2 * kt[0];
-        acc[t][1] += im2 * kt[1];
-        acc[t][2] += im2 * kt[2];
-      }
-    }
+k_phases_T(const cplx* __restrict__ phx, const cplx* __restrict__ phy, const cplx* __restrict__ phz, int n, GridInfo g,
+           cplx* __restrict__ phT) {
+  const int64_t total = (int64_t)n * (g.N[0] + g.N[1] + g.Nh);
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / n;
+    const int64_t q = e - i * n;
+    cplx v;
+    if (i < g.N[0])
+      v = phx[q * g.N[0] + i];
+    else if (i < g.N[0] + g.N[1])
+      v = phy[q * g.N[1] + (i - g.N[0])];
+    else
+      v = phz[q * g.Nh + (i - g.N[0] - g.N[1])];
+    phT[e] = v;
   }
-#pragma unroll
-  for (int t = 0; t < ATILE; ++t)
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      double v = block_sum(acc[t][a], sh);
-      if (threadIdx.x == 0 && t < nj) part[((int64_t)chunk * n_atoms + j0 + t) * 3 + a] = v;
-    }
 }
 
-// F_j = -(2 pi/|Omega|) sum_chunks part + F^pp_j, in fixed chunk order
+// F_j = -(2 pi/|Omega|) sum over the full box of Im(W(k) exp(-2 pi i k.r_j)) k.
+// The half box is walked as rows (ix, iy) by z indices.  A block is one wave:
+// its lanes take 64 atoms (species order), it walks the rows of one row block
+// and, CZ z indices at a time, all of N_h.  Rows go in batches of FRB: the
+// batch's W_s (the same for the whole wave) is staged in LDS, the row phases px,
+// py per lane in registers, and the next batch's loads are in flight while one
+// is summed; the CZ z phases of the lane's atom stay in registers.  Full-box
+// weighting: 2 for 0 < iz < N_z/2 (the mirror -k), 1 at iz = 0 and the z
+// Nyquist index; on a row with a Nyquist x or y index the mirror is k~ instead,
+// with its own weight W-(m) and the Nyquist phase factors conjugated.
+constexpr int FRB = 8;
+constexpr int FORCE_CZ = 16;
+template <int CZ>
+__device__ inline void force_rows_chunk(const cplx* __restrict__ W, const cplx* __restrict__ WM,
+                                        const cplx* __restrict__ xT, const cplx* __restrict__ yT,
+                                        const cplx* __restrict__ zT, int n, int qc, const GridInfo& g, int r0,
+                                        int r1, int iz0, double* f, cplx (*wl)[FRB * FORCE_CZ]) {
+  constexpr int PER = (FRB * CZ + 63) / 64;
+  const int lane = threadIdx.x;
+  cplx pz[CZ];
+#pragma unroll
+  for (int t = 0; t < CZ; ++t) pz[t] = zT[(int64_t)(iz0 + t) * n + qc];
+  // loads of the batch of rows at rb (rows past r1 clamp to r1 - 1; skipped)
+  cplx wn[PER], xn[FRB], yn[FRB];
+  auto fetch = [&](int rb) {
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int e = lane + 64 * p;
+      if (e < FRB * CZ) {
+        const int r = min(rb + e / CZ, r1 - 1);
+        wn[p] = W[(int64_t)r * g.Nh + iz0 + e % CZ];
+      }
+    }
+    int ix = rb / g.N[1], iy = rb - ix * g.N[1];
+#pragma unroll
+    for (int u = 0; u < FRB; ++u) {
+      xn[u] = xT[(int64_t)ix * n + qc];
+      yn[u] = yT[(int64_t)iy * n + qc];
+      // the next row, unless this was the block's last
+      if (rb + u + 1 < r1 && ++iy == g.N[1]) {
+        iy = 0;
+        ++ix;
+      }
+    }
+  };
+  fetch(r0);
+  int buf = 0;
+  for (int rb = r0; rb < r1; rb += FRB, buf ^= 1) {
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int e = lane + 64 * p;
+      if (e < FRB * CZ) wl[buf][e] = wn[p];
+    }
+    cplx xc[FRB], yc[FRB];
+#pragma unroll
+    for (int u = 0; u < FRB; ++u) {
+      xc[u] = xn[u];
+      yc[u] = yn[u];
+    }
+    __syncthreads();
+    if (rb + FRB < r1) fetch(rb + FRB);
+    int ix = rb / g.N[1], iy = rb - ix * g.N[1];
+#pragma unroll
+    for (int u = 0; u < FRB; ++u) {
+      const int r = rb + u;
+      if (r < r1) {
+        const cplx pxy = cmul(xc[u], yc[u]);
+        const bool nx = 2 * ix == g.N[0], ny = 2 * iy == g.N[1];
+        const double kx = (double)box_m(ix, g.N[0]) / g.L[0], ky = (double)box_m(iy, g.N[1]) / g.L[1];
+        const cplx* w = wl[buf] + u * CZ;
+        if (!(nx || ny)) {
+          double sr = 0.0, sz = 0.0;
+#pragma unroll
+          for (int t = 0; t < CZ; ++t) {
+            const int iz = iz0 + t;
+            const cplx wv = w[t];
+            const double Px = pxy.x * pz[t].x - pxy.y * pz[t].y;
+            const double Py = pxy.x * pz[t].y + pxy.y * pz[t].x;
+            const double im = (iz != 0 && 2 * iz != g.N[2] ? 2.0 : 1.0) * (wv.x * Py + wv.y * Px);
+            sr += im;
+            sz += im * (double)iz;
+          }
+          f[0] += sr * kx;
+          f[1] += sr * ky;
+          f[2] += sz / g.L[2];
+        } else {
+          const cplx pxym = cmul(nx ? cconj(xc[u]) : xc[u], ny ? cconj(yc[u]) : yc[u]);
+          const cplx* wm = WM + (int64_t)r * g.Nh + iz0;
+          double sp = 0.0, szp = 0.0, sm = 0.0, szm = 0.0;
+#pragma unroll
+          for (int t = 0; t < CZ; ++t) {
+            const int iz = iz0 + t;
+            const cplx wv = w[t];
+            const double Px = pxy.x * pz[t].x - pxy.y * pz[t].y;
+            const double Py = pxy.x * pz[t].y + pxy.y * pz[t].x;
+            const double im = wv.x * Py + wv.y * Px;
+            sp += im;
+            szp += im * (double)iz;
+            if (iz != 0 && 2 * iz != g.N[2]) {
+              const cplx wmv = wm[t];
+              const double Qx = pxym.x * pz[t].x - pxym.y * pz[t].y;
+              const double Qy = pxym.x * pz[t].y + pxym.y * pz[t].x;
+              const double im2 = wmv.x * Qy + wmv.y * Qx;
+              sm += im2;
+              szm += im2 * (double)iz;
+            }
+          }
+          f[0] += sp * kx + sm * (nx ? -kx : kx);
+          f[1] += sp * ky + sm * (ny ? -ky : ky);
+          f[2] += (szp + szm) / g.L[2];
+        }
+      }
+      if (++iy == g.N[1]) {
+        iy = 0;
+        ++ix;
+      }
+      // keeps the compiler from hoisting the next rows' LDS reads (registers)
+      asm volatile("" ::: "memory");
+    }
+  }
+  __syncthreads();  // the next chunk reuses the buffers
+}
+
+__global__ void __launch_bounds__(64)
+k_force_rows(const cplx* __restrict__ Wp, const cplx* __restrict__ Wm, const cplx* __restrict__ phT,
+             const int* __restrict__ order, const int* __restrict__ spec, int n, GridInfo g, int rows_per_block,
+             double* __restrict__ part /*[row blocks][n][3]*/) {
+  __shared__ cplx wl[2][FRB * FORCE_CZ];
+  const int q = (int)blockIdx.x * 64 + (int)threadIdx.x;
+  const bool live = q < n;
+  const int qc = live ? q : n - 1;
+  const int j = order[qc];
+  const int sj = spec[j];
+  const int s_lo = spec[order[blockIdx.x * 64]];
+  const int s_hi = spec[order[min((int)blockIdx.x * 64 + 63, n - 1)]];
+  const int rows = g.N[0] * g.N[1];
+  const int r0 = (int)blockIdx.y * rows_per_block;
+  const int r1 = min(r0 + rows_per_block, rows);
+  const cplx* xT = phT;
+  const cplx* yT = phT + (int64_t)g.N[0] * n;
+  const cplx* zT = yT + (int64_t)g.N[1] * n;
+  double f[3] = {0.0, 0.0, 0.0};
+  double fs[3];
+  for (int s = s_lo; s <= s_hi; ++s) {
+    // every lane runs every species of its group (the LDS batches are shared);
+    // a lane keeps the sums of its own species
+    const cplx* W = Wp + (int64_t)s * g.nh;
+    const cplx* WM = Wm + (int64_t)s * g.nh;
+    fs[0] = fs[1] = fs[2] = 0.0;
+    int iz0 = 0;
+    for (; iz0 + FORCE_CZ <= g.Nh; iz0 += FORCE_CZ)
+      force_rows_chunk<FORCE_CZ>(W, WM, xT, yT, zT, n, qc, g, r0, r1, iz0, fs, wl);
+    for (; iz0 + 4 <= g.Nh; iz0 += 4) force_rows_chunk<4>(W, WM, xT, yT, zT, n, qc, g, r0, r1, iz0, fs, wl);
+    for (; iz0 < g.Nh; ++iz0) force_rows_chunk<1>(W, WM, xT, yT, zT, n, qc, g, r0, r1, iz0, fs, wl);
+    if (sj == s) {
+      f[0] = fs[0];
+      f[1] = fs[1];
+      f[2] = fs[2];
+    }
+  }
+  if (live) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) part[((int64_t)blockIdx.y * n + j) * 3 + a] = f[a];
+  }
+}
+
+// F_j = -(2 pi/|Omega|) sum_chunks part + F^pp_j, in fixed chunk order: one
+// wave per component, its lanes taking the chunks in a fixed stride
 __global__ void __launch_bounds__(ARCHE_BLOCK)
 k_force_finish(const double* part, int nchunk, int n_atoms, double vol, const double* Fpp, double* F) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= n_atoms * 3) return;
+  const int q = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  if (q >= n_atoms * 3) return;  // whole waves leave together
   double s = 0.0;
-  for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * n_atoms * 3 + q];
-  F[q] = -2.0 * PI / vol * s + Fpp[q];
+  for (int c = lane; c < nchunk; c += 64) s += part[(int64_t)c * n_atoms * 3 + q];
+  s = wave_sum(s);
+  if (lane == 0) F[q] = -2.0 * PI / vol * s + Fpp[q];
 }
 
 // P_ie spectral part: full-box sum of Re(conj(n^) |k| V_s'(|k|) S_s)
@@ -345,14 +584,17 @@ k_pressure_ie(const cplx* nhat, const cplx* Sp, const cplx* Sm, SpeciesInfo sp, 
 // one-center profile (the fit there is ill-conditioned).
 constexpr double SHELL_CUT = 1e-12;
 
-// one-center profile per shell: g = sum Re(n^ conj SZ) / sum |SZ|^2 over the full box
+// one-center profile per shell: g = sum Re(n^ conj SZ) / sum |SZ|^2 over the
+// full box.  One wave per shell: its lanes take the shell's points in a fixed
+// stride and the wave sums them in a fixed order.
 __global__ void __launch_bounds__(ARCHE_BLOCK)
 k_shell_profile(const cplx* nhat, const cplx* SZp, const cplx* SZm, const int* perm, const int* off, int nshell,
                 GridInfo g, double sumZ2, double* gsh) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nshell) return;
+  const int s = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  if (s >= nshell) return;  // whole waves leave together
   double num = 0.0, den = 0.0, cnt = 0.0;
-  for (int q = off[s]; q < off[s + 1]; ++q) {
+  for (int q = off[s] + lane; q < off[s + 1]; q += 64) {
     const int64_t m = perm[q];
     const int iz = (int)(m % g.Nh);
     const cplx n = nhat[m];
@@ -367,7 +609,10 @@ k_shell_profile(const cplx* nhat, const cplx* SZp, const cplx* SZm, const int* p
       cnt += 1.0;
     }
   }
-  gsh[s] = den > SHELL_CUT * cnt * sumZ2 ? num / den : 0.0;
+  num = wave_sum(num);
+  den = wave_sum(den);
+  cnt = wave_sum(cnt);
+  if (lane == 0) gsh[s] = den > SHELL_CUT * cnt * sumZ2 ? num / den : 0.0;
 }
 
 // n^_i(m) = g(shell(m)) (SZ+(m) + SZ-(m))/2
@@ -499,15 +744,15 @@ k_stress_recip(const cplx* nhat, const cplx* shat, const cplx* Sp, const cplx* S
 
 // Ewald real-space pair tensor, per atom j: (1/2) sum_{l != j} Z_j Z_l
 // [erfc(alpha d)/d + 2 alpha/sqrt(pi) exp(-alpha^2 d^2)] d_mu d_nu / d^2 (minimum image),
-// six components per atom [j][6]
+// six components per atom [j][6]; one block per atom, as k_ewald_pairs
 __global__ void __launch_bounds__(ARCHE_BLOCK)
 k_ewald_pair_stress(const double* pos, const double* Zat, int n, GridInfo g, double alpha, double* out) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
+  __shared__ double sh[(ARCHE_BLOCK / 64) * 6];
+  const int j = blockIdx.x;
   const double xj = pos[3 * j], yj = pos[3 * j + 1], zj = pos[3 * j + 2];
   const double c2 = 2.0 * alpha / sqrt(PI);
   double o[6] = {0, 0, 0, 0, 0, 0};
-  for (int l = 0; l < n; ++l) {
+  for (int l = threadIdx.x; l < n; l += blockDim.x) {
     if (l == j) continue;
     double d[3] = {xj - pos[3 * l], yj - pos[3 * l + 1], zj - pos[3 * l + 2]};
     for (int a = 0; a < 3; ++a) d[a] -= g.L[a] * rint(d[a] / g.L[a]);
@@ -516,7 +761,9 @@ k_ewald_pair_stress(const double* pos, const double* Zat, int n, GridInfo g, dou
     const double coef = 0.5 * Zat[j] * Zat[l] * (erfc(alpha * r) / r + c2 * exp(-alpha * alpha * r2)) / r2;
     kk6(d, coef, o);
   }
-  for (int q = 0; q < 6; ++q) out[(size_t)q * n + j] = o[q];
+  block_reduce_n<6>(o, 0u, sh);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 6; ++q) out[(size_t)q * n + j] = o[q];
 }
 
 }  // namespace
@@ -534,10 +781,15 @@ double ewald_alpha(const arche_ctx* c) {
 hipError_t ionic_structure(arche_ctx* c) {
   const GridInfo& g = c->g;
   hipLaunchKernelGGL(k_phases, dim3(grid_for((int64_t)c->n_atoms * (g.N[0] + g.N[1] + g.Nh))), dim3(ARCHE_BLOCK), 0,
-                     c->stream, c->pos, c->n_atoms, g, c->phx, c->phy, c->phz);
+                     c->stream, c->pos, c->sp_order, c->n_atoms, g, c->phx, c->phy, c->phz);
   HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_structure, dim3(grid_for(g.nh)), dim3(ARCHE_BLOCK), 0, c->stream, c->phx, c->phy, c->phz,
-                     c->sp_order, c->sp_begin, c->n_species, g, c->Sp, c->Sm);
+  const int rows = g.N[0] * g.N[1];
+  const unsigned nzc = (unsigned)((g.Nh + SZ_CZ - 1) / SZ_CZ);
+  const int nrx = (g.N[0] % 2 == 0) ? g.N[1] : 0;
+  const int nry = (g.N[1] % 2 == 0) ? g.N[0] - (g.N[0] % 2 == 0 ? 1 : 0) : 0;
+  const unsigned mb = (unsigned)((rows + 63) / 64), nb = (unsigned)((nrx + nry + 63) / 64);
+  hipLaunchKernelGGL(k_structure_rows, dim3(mb + nb, nzc), dim3(64), 0, c->stream, c->phx, c->phy, c->phz,
+                     c->sp_begin, c->n_species, g, mb, nrx + nry, c->Sp, c->Sm);
   HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_vie_hat, dim3(grid_for(g.nh)), dim3(ARCHE_BLOCK), 0, c->stream, c->Sp, c->Sm, c->sp, g, c->SZp,
                      c->SZm, c->ctmp);
@@ -550,7 +802,7 @@ hipError_t ionic_ewald(arche_ctx* c, double* U3, double alpha) {
   const GridInfo& g = c->g;
   const int n = c->n_atoms;
   double* Uj = c->partials;
-  hipLaunchKernelGGL(k_ewald_pairs, dim3((n + ARCHE_BLOCK - 1) / ARCHE_BLOCK), dim3(ARCHE_BLOCK), 0, c->stream, c->pos,
+  hipLaunchKernelGGL(k_ewald_pairs, dim3(n), dim3(ARCHE_BLOCK), 0, c->stream, c->pos,
                      c->Zatom, n, g, alpha, c->fpp, Uj);
   HIP_TRY(hipGetLastError());
   HIP_TRY(finish_sums(Uj, n, 1, c->sums, c->stream));
@@ -568,6 +820,17 @@ hipError_t ionic_ewald(arche_ctx* c, double* U3, double alpha) {
   return hipSuccess;
 }
 
+// Row blocks of the force kernel: about 4096 waves in all (atom groups of 64 x
+// row blocks), *rows_per_block rows each.
+static int force_row_blocks(const arche_ctx* c, int* rows_per_block) {
+  const int64_t rows = (int64_t)c->g.N[0] * c->g.N[1];
+  const int64_t groups = (c->n_atoms + 63) / 64;
+  const int64_t want = std::max<int64_t>(1, std::min<int64_t>(rows, 4096 / groups));
+  const int64_t rpb = (rows + want - 1) / want;
+  *rows_per_block = (int)rpb;
+  return (int)((rows + rpb - 1) / rpb);
+}
+
 // forces (device [n][3]) from the converged spectrum nhat; needs ionic_ewald first (F^pp)
 hipError_t ionic_forces(arche_ctx* c, const cplx* nhat, double* forces_dev) {
   const GridInfo& g = c->g;
@@ -575,19 +838,23 @@ hipError_t ionic_forces(arche_ctx* c, const cplx* nhat, double* forces_dev) {
   hipLaunchKernelGGL(k_force_weights, dim3(grid_for(g.nh)), dim3(ARCHE_BLOCK), 0, c->stream, nhat, c->SZp, c->SZm,
                      c->sp, g, alpha, c->Wp, c->Wm);
   HIP_TRY(hipGetLastError());
-  const int nchunk = (int)((g.nh + MCHUNK - 1) / MCHUNK);
-  const int ntile = (c->n_atoms + ATILE - 1) / ATILE;
-  hipLaunchKernelGGL(k_force_contract, dim3(nchunk, ntile), dim3(ARCHE_BLOCK), 0, c->stream, c->Wp, c->Wm, c->phx,
-                     c->phy, c->phz, c->spec_d, c->n_atoms, g, c->fpart);
+  const int n = c->n_atoms;
+  hipLaunchKernelGGL(k_phases_T, dim3(grid_for((int64_t)n * (g.N[0] + g.N[1] + g.Nh))), dim3(ARCHE_BLOCK), 0, c->stream,
+                     c->phx, c->phy, c->phz, n, g, c->phT);
   HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_force_finish, dim3((3 * c->n_atoms + ARCHE_BLOCK - 1) / ARCHE_BLOCK), dim3(ARCHE_BLOCK), 0,
-                     c->stream, c->fpart, nchunk, c->n_atoms, g.vol, c->fpp, forces_dev);
+  int rpb = 0;
+  const int nrb = force_row_blocks(c, &rpb);
+  hipLaunchKernelGGL(k_force_rows, dim3((unsigned)((n + 63) / 64), (unsigned)nrb), dim3(64), 0, c->stream, c->Wp, c->Wm,
+                     c->phT, c->sp_order, c->spec_d, n, g, rpb, c->fpart);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_force_finish, dim3((3 * n + ARCHE_BLOCK / 64 - 1) / (ARCHE_BLOCK / 64)), dim3(ARCHE_BLOCK), 0,
+                     c->stream, c->fpart, nrb, n, g.vol, c->fpp, forces_dev);
   return hipGetLastError();
 }
 
 size_t ionic_force_partials(const arche_ctx* c) {
-  const int nchunk = (int)((c->g.nh + MCHUNK - 1) / MCHUNK);
-  return (size_t)nchunk * c->n_atoms * 3;
+  int rpb = 0;
+  return (size_t)force_row_blocks(c, &rpb) * c->n_atoms * 3;
 }
 
 // spectral part of P_ie (host out)
@@ -674,7 +941,7 @@ hipError_t scf_floor_renorm(arche_ctx* c, double* n, bool* ok) {
 hipError_t scf_one_center_density(arche_ctx* c, int* used_fallback, double* raw, double* delta) {
   const GridInfo& g = c->g;
   *used_fallback = 0;
-  hipLaunchKernelGGL(k_shell_profile, dim3((c->nshell + ARCHE_BLOCK - 1) / ARCHE_BLOCK), dim3(ARCHE_BLOCK), 0,
+  hipLaunchKernelGGL(k_shell_profile, dim3((c->nshell + ARCHE_BLOCK / 64 - 1) / (ARCHE_BLOCK / 64)), dim3(ARCHE_BLOCK), 0,
                      c->stream, c->prev_nhat, c->prev_SZp, c->prev_SZm, c->shell_perm, c->shell_off, c->nshell, g,
                      c->sumZ2, c->shell_g);
   HIP_TRY(hipGetLastError());
@@ -763,7 +1030,7 @@ hipError_t ionic_stress_sums(arche_ctx* c, const cplx* nhat, const cplx* shat, d
   const int n = c->n_atoms;
   double* pp = c->partials;
   double* part = c->partials + 6 * (size_t)n;
-  hipLaunchKernelGGL(k_ewald_pair_stress, dim3((n + ARCHE_BLOCK - 1) / ARCHE_BLOCK), dim3(ARCHE_BLOCK), 0,
+  hipLaunchKernelGGL(k_ewald_pair_stress, dim3(n), dim3(ARCHE_BLOCK), 0,
                      c->stream, c->pos, c->Zatom, n, g, alpha, pp);
   HIP_TRY(hipGetLastError());
   HIP_TRY(finish_sums(pp, n, 6, c->sums, c->stream));

@@ -21,6 +21,8 @@ struct Profiler {
   double total_ms[PROF_KINDS] = {0, 0, 0};
   long long launches[PROF_KINDS] = {0, 0, 0};
   unsigned mask = ~0u;  // kinds that are timed (each timed launch adds an event pair)
+  int every = 1;         // time one launch in `every` of each kind
+  long long seen[PROF_KINDS] = {0, 0, 0};
 
   hipEvent_t take() {
     if (used == pool.size()) {
@@ -56,6 +58,7 @@ struct ProfScope {
   hipStream_t s;
   ProfScope(int k, hipStream_t st) : p(g_profiler), kind(k), s(st) {
     if (p && !((p->mask >> k) & 1u)) p = nullptr;
+    if (p && p->every > 1 && (p->seen[k]++ % p->every) != 0) p = nullptr;
     if (!p) return;
     if (p->open.size() > 8192) p->collect();
     hipEvent_t a = p->take();

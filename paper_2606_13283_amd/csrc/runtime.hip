@@ -84,7 +84,7 @@ void free_all(arche_ctx* c) {
   void* ptrs[] = {c->ff_d, c->Vie, c->VH, c->lap_i, c->n_i, c->n_a, c->Vi, c->lap_a, c->rtmp, c->nhat_i, c->nhat_a, c->ctmp,
                   c->ctmp2, c->Sp, c->Sm, c->SZp, c->SZm, c->prev_nhat, c->prev_SZp, c->prev_SZm, c->shell_of,
                   c->shell_perm, c->shell_off, c->shell_g, c->pos, c->Zatom, c->forces, c->fpp, c->fpart, c->spec_d,
-                  c->sp_order, c->sp_begin, c->Wp, c->Wm, c->phx, c->phy, c->phz, c->partials, c->sums, c->state,
+                  c->sp_order, c->sp_begin, c->Wp, c->Wm, c->phx, c->phy, c->phz, c->phT, c->partials, c->sums, c->state,
                   c->bar, c->err_d};
   for (void* p : ptrs) c->dalloc_.put(p, c->stream);
   if (c->state_host) (void)hipHostFree(c->state_host);
@@ -539,6 +539,7 @@ arche_status arche_scf_init(const arche_params* p, void* hip_stream, arche_ctx**
   ok = ok && dalloc(c, &c->phx, (size_t)n * g.N[0]) == hipSuccess;
   ok = ok && dalloc(c, &c->phy, (size_t)n * g.N[1]) == hipSuccess;
   ok = ok && dalloc(c, &c->phz, (size_t)n * g.Nh) == hipSuccess;
+  ok = ok && dalloc(c, &c->phT, (size_t)n * (g.N[0] + g.N[1] + g.Nh)) == hipSuccess;
   ok = ok && dalloc(c, &c->pos, 3 * (size_t)n) == hipSuccess;
   ok = ok && dalloc(c, &c->Zatom, (size_t)n) == hipSuccess;
   ok = ok && dalloc(c, &c->forces, 3 * (size_t)n) == hipSuccess;
@@ -550,7 +551,7 @@ arche_status arche_scf_init(const arche_params* p, void* hip_stream, arche_ctx**
   ok = ok && dalloc(c, &c->partials, (size_t)c->partial_cap) == hipSuccess;
   ok = ok && dalloc(c, &c->sums, 64) == hipSuccess;
   ok = ok && dalloc(c, &c->state, 1) == hipSuccess;
-  ok = ok && dalloc(c, &c->bar, (size_t)c->coop_blocks + 1) == hipSuccess;
+  ok = ok && dalloc(c, &c->bar, (size_t)SCF_BAR_WORDS) == hipSuccess;
   ok = ok && dalloc(c, &c->err_d, 1) == hipSuccess;
   if (ok) ok = dalloc(c, &c->fpart, ionic_force_partials(c)) == hipSuccess;
   if (ok && !c->ff_host.empty()) ok = dalloc(c, &c->ff_d, c->ff_host.size()) == hipSuccess;
@@ -870,6 +871,13 @@ arche_status arche_profile_enable(arche_ctx* c, int32_t on) {
   return ARCHE_OK;
 }
 
+arche_status arche_profile_sample(arche_ctx* c, int32_t every) {
+  if (!c || every < 1) return ARCHE_EINVAL;
+  if (!c->prof) return set_err(c, ARCHE_ESTATE, "profiling is not enabled");
+  c->prof->every = every;
+  return ARCHE_OK;
+}
+
 arche_status arche_profile_read(arche_ctx* c, int32_t kind, double* total_ms, int64_t* launches) {
   if (!c || !total_ms || !launches || kind < 0 || kind >= PROF_KINDS) return ARCHE_EINVAL;
   if (!c->prof) return set_err(c, ARCHE_ESTATE, "profiling is not enabled");
@@ -884,6 +892,7 @@ arche_status arche_profile_reset(arche_ctx* c) {
     for (int k = 0; k < PROF_KINDS; ++k) {
       c->prof->total_ms[k] = 0.0;
       c->prof->launches[k] = 0;
+      c->prof->seen[k] = 0;
     }
   }
   return ARCHE_OK;

@@ -13,14 +13,19 @@ namespace {
 constexpr double PI = 3.14159265358979323846;
 
 
-// The grid is cut into nchunk chunks of SCF_CHUNK points: the grid is read as
-// PPT stripes of nchunk*ARCHE_BLOCK points, and chunk c takes the c-th run of
-// ARCHE_BLOCK consecutive points in each stripe (thread t the t-th of each).  A
+// The SCF kernel runs blocks of SCF_THREADS threads.  The grid is cut into
+// nchunk chunks of SCF_CHUNK points: the grid is read as PPT stripes of
+// nchunk*SCF_THREADS points, and chunk c takes the c-th run of SCF_THREADS
+// consecutive points in each stripe (thread t the t-th of each).  A
 // chunk thus samples the whole cell, and blocks near ions and between them carry
 // the same mix of work; each wave still reads 64 consecutive values.  Every
 // global sum is a sum of per-chunk partials in chunk order, so the result does
 // not depend on how many blocks share the work (a batched solve, with fewer
-// blocks per snapshot, is bit-identical to an unbatched one).
+// blocks per snapshot, is bit-identical to an unbatched one).  The kernel's
+// FP64 evaluations need about 200 registers per lane, so two waves per SIMD
+// (two blocks per CU, whose LDS caches then fill the CU) is what fits without
+// spilling.
+constexpr int SCF_THREADS = 256;
 constexpr int PPT = 16;
 // More's weight may switch on once mu moves by at most this fraction of kT
 // between iterations (the chemical-potential fluctuations of Sec. 2.5.2 are small)
@@ -28,18 +33,18 @@ constexpr double MU_SETTLED = 0.02;
 // More's weight may fall by at most this much from one iteration to the next
 // (the quadratic model can send it to 0 in one step in low-density regions)
 constexpr double W_MAX_DROP = 0.05;
-constexpr int SCF_CHUNK = ARCHE_BLOCK * PPT;
+constexpr int SCF_CHUNK = SCF_THREADS * PPT;
 // the chemical potential is found once |N(mu) - N_e| <= MU_TOL N_e
 constexpr double MU_TOL = 1e-14;
 // after a Newton evaluation with |N - N_e| <= SPEC_NEWTON N_e the next pass is
 // most likely the last (quadratic convergence) and forms the active sums too
 constexpr double SPEC_NEWTON = 1e-7;
 // LDS doubles for block_reduce_n<8>
-constexpr int RED_SH = (ARCHE_BLOCK / 64) * 8;
+constexpr int RED_SH = (SCF_THREADS / 64) * 8;
 
 // point q of this thread in chunk c (>= ng: none)
 __device__ inline int64_t chunk_point(const ActiveArgs& a, int64_t c, int q) {
-  return (int64_t)q * (a.nchunk * ARCHE_BLOCK) + c * ARCHE_BLOCK + threadIdx.x;
+  return (int64_t)q * (a.nchunk * SCF_THREADS) + c * SCF_THREADS + threadIdx.x;
 }
 
 // The first NV block-reduced values of acc go to slots s0.. of chunk c.
@@ -95,7 +100,7 @@ __device__ inline void vxc_group(const double* n, double* v) {
 //   slots 2..7: sum dn^2, sum n_a^2, K, U_xc, sum n_a, max |dn|/n_a
 //   (dn = n_i - n_a; K is the secant of the Thomas-Fermi potential kT eta(n)
 //   between n_a and n_i, U_xc the same for v_xc)
-// With CACHE, vls and xls (LDS, [PPT][ARCHE_BLOCK]) hold the block's V_i and
+// With CACHE, vls and xls (LDS, [PPT][SCF_THREADS]) hold the block's V_i and
 // v_xc(n_i) from the assembly.
 template <bool CACHE, bool ACTIVE>
 __device__ inline void chunk_sums(const ActiveArgs& a, int64_t c, const double* vls, const double* xls, double mu,
@@ -115,7 +120,7 @@ __device__ inline void chunk_sums(const ActiveArgs& a, int64_t c, const double* 
       const int64_t i = chunk_point(a, c, q0 + g);
       ok[g] = i < a.ng;
       ip[g] = ok[g] ? i : a.ng - 1;
-      const double v = CACHE ? vls[(q0 + g) * ARCHE_BLOCK + threadIdx.x] : a.Vi[ip[g]];
+      const double v = CACHE ? vls[(q0 + g) * SCF_THREADS + threadIdx.x] : a.Vi[ip[g]];
       x[g] = (mu - v) * ikT;
       if (ACTIVE) ni[g] = a.n_i[ip[g]];
     }
@@ -162,7 +167,7 @@ __device__ inline void chunk_sums(const ActiveArgs& a, int64_t c, const double* 
         vxc_group(na, va);
         if (CACHE) {
 #pragma unroll
-          for (int g = 0; g < PG; ++g) vi[g] = xls[(q0 + g) * ARCHE_BLOCK + threadIdx.x];
+          for (int g = 0; g < PG; ++g) vi[g] = xls[(q0 + g) * SCF_THREADS + threadIdx.x];
         } else {
           vxc_group(ni, vi);
         }
@@ -201,8 +206,13 @@ template <bool CACHE>
 __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigned G, const FdLds& fdl, double* sh,
                                        double* r, double* vls, double* xls) {
   ScfState* st = a.st;
-  unsigned* go = a.flags + G;
-  unsigned epoch = (unsigned)(st->iter + 1) * 256u;  // grows by one per all-reduce; disjoint per launch
+  // arrival counters: launches alternate between two banks; block 0 clears the
+  // bank of the next launch (this launch does not touch it, the previous one
+  // has ended)
+  unsigned* bank = a.flags + ARRIVE_BANK * (unsigned)(st->iter & 1);
+  if (lb == 0 && threadIdx.x < ARRIVE_BANK)
+    coherent_store_u32(a.flags + ARRIVE_BANK * (unsigned)((st->iter + 1) & 1) + threadIdx.x, 0u);
+  unsigned nred = 0;  // all-reduces of this launch so far
   const int64_t nchunk = a.nchunk;
   const double kT = a.kT;
   const double ikT = 1.0 / kT;
@@ -239,8 +249,8 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
         v[g] += vx[g];
         if (a.lam != 0.0) v[g] += -0.5 * a.lam * lp[g] / sqrt(n[g]);
         if (CACHE) {
-          vls[(q0 + g) * ARCHE_BLOCK + threadIdx.x] = v[g];
-          xls[(q0 + g) * ARCHE_BLOCK + threadIdx.x] = vx[g];
+          vls[(q0 + g) * SCF_THREADS + threadIdx.x] = v[g];
+          xls[(q0 + g) * SCF_THREADS + threadIdx.x] = vx[g];
         } else if (ok[g]) {
           a.Vi[chunk_point(a, c, q0 + g)] = v[g];
         }
@@ -265,7 +275,7 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
     block_reduce_n<7>(acc, 0x6u, sh);
     put_chunk_n<7>(acc, a.part, 0, nchunk, c);
   }
-  grid_allreduce(a.part, nchunk, a.res, 0, try_prev ? 7 : 3, 0x6u, G, lb, a.flags, go, ++epoch, a.err, r, sh);
+  grid_allreduce(a.part, nchunk, a.res, 0, try_prev ? 7 : 3, 0x6u, G, lb, bank, ++nred, a.err, r, sh);
   const double Vsum = r[0], Vmax = r[1], Vmin = -r[2];
   const double scale = a.dv * a.cn;  // N = scale * sum I_{1/2}
   double lo = Vmin + kT * a.eta0;
@@ -319,10 +329,10 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
     ++it;
     if (spec) {
       FOR_CHUNKS(c) chunk_sums<CACHE, true>(a, c, vls, xls, mu, ikT, fdl, sh);
-      grid_allreduce(a.part, nchunk, a.res, 0, 8, 0x80u, G, lb, a.flags, go, ++epoch, a.err, r, sh);
+      grid_allreduce(a.part, nchunk, a.res, 0, 8, 0x80u, G, lb, bank, ++nred, a.err, r, sh);
     } else {
       FOR_CHUNKS(c) chunk_sums<CACHE, false>(a, c, vls, xls, mu, ikT, fdl, sh);
-      grid_allreduce(a.part, nchunk, a.res, 0, 2, 0u, G, lb, a.flags, go, ++epoch, a.err, r, sh);
+      grid_allreduce(a.part, nchunk, a.res, 0, 2, 0u, G, lb, bank, ++nred, a.err, r, sh);
     }
     N = scale * r[0];
     dN = scale * ikT * r[1];
@@ -353,7 +363,7 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
   // 3. active density and the mixing reductions (unless the last pass formed them)
   if (!have_sums) {
     FOR_CHUNKS(c) chunk_sums<CACHE, true>(a, c, vls, xls, mu, ikT, fdl, sh);
-    grid_allreduce(a.part, nchunk, a.res, 0, 8, 0x80u, G, lb, a.flags, go, ++epoch, a.err, r, sh);
+    grid_allreduce(a.part, nchunk, a.res, 0, 8, 0x80u, G, lb, bank, ++nred, a.err, r, sh);
     for (int k = 0; k < 6; ++k) D[k] = r[2 + k];
   }
   const double DD = D[0], NN = D[1], KK = D[2], UU = D[3], NA = D[4], MX = D[5];
@@ -365,7 +375,7 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
     FOR_CHUNKS(c) {
       for (int q = 0; q < PPT; ++q) {
         const int64_t i = chunk_point(a, c, q);
-        if (i < a.ng) a.Vi[i] = vls[q * ARCHE_BLOCK + threadIdx.x];
+        if (i < a.ng) a.Vi[i] = vls[q * SCF_THREADS + threadIdx.x];
       }
     }
   }
@@ -398,11 +408,11 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
 
 // One system: the whole cooperative grid is the group.
 template <bool CACHE>
-__global__ void __launch_bounds__(ARCHE_BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) k_scf_active(ActiveArgs a) {
+__global__ void __launch_bounds__(SCF_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) k_scf_active(ActiveArgs a) {
   __shared__ double sh[RED_SH];
   __shared__ double r[8];
   __shared__ FdLds fdl;
-  __shared__ double vls[CACHE ? PPT * ARCHE_BLOCK : 1], xls[CACHE ? PPT * ARCHE_BLOCK : 1];
+  __shared__ double vls[CACHE ? PPT * SCF_THREADS : 1], xls[CACHE ? PPT * SCF_THREADS : 1];
   if (a.st->done) return;
   fd_lds_load(&fdl, a.fdt);
   __syncthreads();
@@ -411,12 +421,12 @@ __global__ void __launch_bounds__(ARCHE_BLOCK) __attribute__((amdgpu_waves_per_e
 
 // Many systems in one cooperative launch: system s owns blocks
 // [group_begin[s], group_begin[s+1]) (its group), converged systems drop out.
-__global__ void __launch_bounds__(ARCHE_BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2)))
+__global__ void __launch_bounds__(SCF_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_scf_active_batch(const ActiveArgs* __restrict__ args, const int* __restrict__ group_begin, int nsys) {
   __shared__ double sh[RED_SH];
   __shared__ double r[8];
   __shared__ FdLds fdl;
-  __shared__ double vls[PPT * ARCHE_BLOCK], xls[PPT * ARCHE_BLOCK];
+  __shared__ double vls[PPT * SCF_THREADS], xls[PPT * SCF_THREADS];
   int s = 0;
   while (s + 1 < nsys && group_begin[s + 1] <= (int)blockIdx.x) ++s;
   const ActiveArgs a = args[s];
@@ -747,7 +757,7 @@ const FdTables* fd_tables_device(int device) {
 }
 
 hipError_t scf_reset_state(arche_ctx* c, double mu0) {
-  hipLaunchKernelGGL(k_state_init, dim3(4), dim3(ARCHE_BLOCK), 0, c->stream, c->state, c->bar, c->coop_blocks + 1,
+  hipLaunchKernelGGL(k_state_init, dim3(4), dim3(ARCHE_BLOCK), 0, c->stream, c->state, c->bar, SCF_BAR_WORDS,
                      c->err_d, mu0);
   return hipGetLastError();
 }
@@ -802,8 +812,8 @@ int scf_coop_blocks(int64_t ng) {
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
   int per_cu = 0, per_cu2 = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_scf_active<true>, ARCHE_BLOCK, 0) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu2, k_scf_active<false>, ARCHE_BLOCK, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_scf_active<true>, SCF_THREADS, 0) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu2, k_scf_active<false>, SCF_THREADS, 0) != hipSuccess)
     return 0;
   per_cu = std::min(per_cu, per_cu2);
   int64_t b = std::min<int64_t>((int64_t)per_cu * cus, 2 * (int64_t)cus);
@@ -840,7 +850,7 @@ static ActiveArgs active_args(const arche_ctx* c) {
   a.mixing = p.mixing;
   a.warmup = p.more_warmup;
   a.trust = p.more_trust;
-  a.max_newton = 200;  // < 250 all-reduces per launch keeps the epochs of launches disjoint
+  a.max_newton = 200;
   a.max_iter = p.scf_max_iter;
   return a;
 }
@@ -1055,13 +1065,13 @@ hipError_t scf_iteration(arche_ctx* c) {
     // raises the error flag instead of hanging).
     if (scf_plain_launch(c)) {
       if (cache)
-        hipLaunchKernelGGL(k_scf_active<true>, dim3(c->coop_blocks), dim3(ARCHE_BLOCK), 0, c->stream, c->active);
+        hipLaunchKernelGGL(k_scf_active<true>, dim3(c->coop_blocks), dim3(SCF_THREADS), 0, c->stream, c->active);
       else
-        hipLaunchKernelGGL(k_scf_active<false>, dim3(c->coop_blocks), dim3(ARCHE_BLOCK), 0, c->stream, c->active);
+        hipLaunchKernelGGL(k_scf_active<false>, dim3(c->coop_blocks), dim3(SCF_THREADS), 0, c->stream, c->active);
       HIP_TRY(hipGetLastError());
     } else {
       HIP_TRY(hipLaunchCooperativeKernel(cache ? (const void*)k_scf_active<true> : (const void*)k_scf_active<false>,
-                                         dim3(c->coop_blocks), dim3(ARCHE_BLOCK), args, 0, c->stream));
+                                         dim3(c->coop_blocks), dim3(SCF_THREADS), args, 0, c->stream));
     }
   }
   if (!c->fused) return scf_iteration_rest_plain(c);
@@ -1075,7 +1085,7 @@ int scf_batch_capacity() {
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_scf_active_batch, ARCHE_BLOCK, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_scf_active_batch, SCF_THREADS, 0) != hipSuccess)
     return 0;
   return per_cu * cus;
 }
@@ -1084,7 +1094,7 @@ hipError_t scf_active_batch_launch(const ActiveArgs* args, const int* group_begi
                                    hipStream_t s) {
   void* kargs[] = {&args, &group_begin, &nsys};
   ProfScope prof(PROF_SCF_ACTIVE, s);
-  return hipLaunchCooperativeKernel((const void*)k_scf_active_batch, dim3(nblocks), dim3(ARCHE_BLOCK), kargs, 0, s);
+  return hipLaunchCooperativeKernel((const void*)k_scf_active_batch, dim3(nblocks), dim3(SCF_THREADS), kargs, 0, s);
 }
 
 hipError_t scf_weight_batch_launch(const MixWeightArgs* jobs, int njobs, hipStream_t s) {
