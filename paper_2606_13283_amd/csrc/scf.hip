@@ -99,13 +99,15 @@ __device__ inline void vxc_group(const double* n, double* v) {
 // and with ACTIVE, which also stores n_a = c_n I_{1/2}(eta):
 //   slots 2..7: sum dn^2, sum n_a^2, K, U_xc, sum n_a, max |dn|/n_a
 //   (dn = n_i - n_a; K is the secant of the Thomas-Fermi potential kT eta(n)
-//   between n_a and n_i, U_xc the same for v_xc)
+//   between n_a and n_i, U_xc the same for v_xc; both only with with_k, else 0:
+//   the secant K inverts I_{1/2} at n_i, costly while n_i and n_a are far apart,
+//   and only More's weight uses it)
 // With CACHE, vls and xls (LDS, [PPT][SCF_THREADS]) hold the block's V_i and
 // v_xc(n_i) from the assembly.
 template <bool CACHE, bool ACTIVE>
 __device__ inline void chunk_sums(const ActiveArgs& a, int64_t c, const double* vls, const double* xls, double mu,
-                                  double ikT, const FdLds& fdl, double* sh) {
-  const bool more = a.mixing == ARCHE_MIX_MORE;  // secant K and U_xc
+                                  double ikT, const FdLds& fdl, double* sh, bool with_k = true) {
+  const bool more = a.mixing == ARCHE_MIX_MORE && with_k;  // secant K and U_xc
   const bool printed = a.mixing == ARCHE_MIX_MORE_PRINTED;  // K = int dn^2 / (dn_a/dmu)
   const double icn = 1.0 / a.cn;
   constexpr int D = ACTIVE ? 3 : 1;
@@ -150,9 +152,19 @@ __device__ inline void chunk_sums(const ActiveArgs& a, int64_t c, const double* 
           anyfar |= far[g] && ok[g];
         }
         if (anyfar) {
+          // moderate shifts by the cubic model polished with one Newton step,
+          // larger ones by the full inversion
+          bool farther[PG], anyfarther = false;
 #pragma unroll
-          for (int g = 0; g < PG; ++g)
-            if (far[g] && ok[g]) sh_[g] = fd_p12_inverse_from(fdl, ni[g] * icn, x[g], d[g][0], d[g][1]) - x[g];
+          for (int g = 0; g < PG; ++g) {
+            farther[g] = far[g] && ok[g] && !fd_p12_shift_near(fdl, ni[g] * icn, x[g], d[g], sh_[g]);
+            anyfarther |= farther[g];
+          }
+          if (anyfarther) {
+#pragma unroll
+            for (int g = 0; g < PG; ++g)
+              if (farther[g]) sh_[g] = fd_p12_inverse_from(fdl, ni[g] * icn, x[g], d[g][0], d[g][1]) - x[g];
+          }
         }
 #pragma unroll
         for (int g = 0; g < PG; ++g) acc[4] += ok[g] ? a.kT * sh_[g] * dn[g] : 0.0;  // kT (eta_i - eta_a) dn
@@ -189,11 +201,13 @@ __device__ inline void chunk_sums(const ActiveArgs& a, int64_t c, const double* 
 // co-resident blocks (lb = this block's index in the group).
 //   1. V_i = V^ie + V_H + v_xc(n_i) + v_vW[n_i] with its sum, max and min, and
 //      at the previous iteration's mu the sums of I_{1/2} and of its first
-//      three derivatives: N(mu) and its cubic Taylor model about that mu
-//   2. Newton search of mu (safeguarded by bisection) for N(mu) = N_e,
+//      three derivatives: N(mu) and the cubic Taylor model of ln N about that mu
+//   2. Newton search of mu (safeguarded by bisection) for ln N(mu) = ln N_e,
 //      started from the root of the cubic model: mu moves little between
 //      iterations, so the model's root is usually exact to MU_TOL and one pass
-//      confirms it
+//      confirms it; in the first iterations, where mu moves by several kT,
+//      ln N (nearly linear in mu where N grows exponentially) keeps the steps
+//      few where Newton on N itself would advance about kT per pass
 //   3. n_a at mu with the sums of the residual and of More's weight; a Newton
 //      pass that is expected to be the last forms them too, so when it
 //      converges no separate pass is needed
@@ -206,13 +220,21 @@ template <bool CACHE>
 __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigned G, const FdLds& fdl, double* sh,
                                        double* r, double* vls, double* xls) {
   ScfState* st = a.st;
+  // the state as the launch found it, read before the first all-reduce: block 0
+  // advances it after the last one, while other blocks may still be on their
+  // way out of that all-reduce
+  const int t = st->iter;
   // arrival counters: launches alternate between two banks; block 0 clears the
   // bank of the next launch (this launch does not touch it, the previous one
   // has ended)
-  unsigned* bank = a.flags + ARRIVE_BANK * (unsigned)(st->iter & 1);
+  unsigned* bank = a.flags + ARRIVE_BANK * (unsigned)(t & 1);
   if (lb == 0 && threadIdx.x < ARRIVE_BANK)
-    coherent_store_u32(a.flags + ARRIVE_BANK * (unsigned)((st->iter + 1) & 1) + threadIdx.x, 0u);
+    coherent_store_u32(a.flags + ARRIVE_BANK * (unsigned)((t + 1) & 1) + threadIdx.x, 0u);
   unsigned nred = 0;  // all-reduces of this launch so far
+  // K and U_xc are formed with the active density only once More's weight is on;
+  // in the iteration where it switches on they take a pass of their own
+  const bool k_on = st->more_on != 0;
+  const int more_on0 = st->more_on;
   const int64_t nchunk = a.nchunk;
   const double kT = a.kT;
   const double ikT = 1.0 / kT;
@@ -302,8 +324,12 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
       else
         lo = mu;
       // root z = (mu - mu_prev)/kT of g(z) = g0 + g1 z + g2 z^2 + g3 z^3, the
-      // cubic Taylor model of (N(mu) - N_e)/scale, by Newton from z = 0
-      const double g0 = r[3] - a.Ne / scale, g1 = r[4], g2 = 0.5 * r[5], g3 = r[6] / 6.0;
+      // cubic Taylor model of ln N(mu) - ln N_e, by Newton from z = 0 (ln N is
+      // nearly linear where N grows exponentially in mu, so the model holds
+      // over shifts of several kT)
+      const double u1 = r[4] / r[3], u2 = r[5] / r[3], u3 = r[6] / r[3];
+      const double g0 = log(r[3]) - log(a.Ne / scale), g1 = u1, g2 = 0.5 * (u2 - u1 * u1),
+                   g3 = (u3 - 3.0 * u1 * u2 + 2.0 * u1 * u1 * u1) / 6.0;
       double z = 0.0;
       for (int k = 0; k < 8; ++k) {
         const double gz = fma(z, fma(z, fma(z, g3, g2), g1), g0);
@@ -313,12 +339,13 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
         if (fabs(s) <= 1e-16 * (1.0 + fabs(z))) break;
       }
       double mn = mu + kT * z;
-      // the model's error is of order z^4/24 of N (the non-degenerate bound,
-      // where every derivative of I_{1/2} equals I_{1/2}); when that is within
-      // MU_TOL the pass at the root forms the active sums as well
+      // the model's error is of order z^4/24 (relative to N; bounded by the
+      // model of N itself, whose derivatives in the non-degenerate limit all
+      // equal N); when that is within MU_TOL the pass at the root forms the
+      // active sums as well
       spec = z * z * z * z * (1.0 / 24.0) <= 0.5 * MU_TOL;
       if (!(lo < mn && mn < hi)) {
-        mn = mu - f / dN;
+        mn = mu - (log(N) - log(a.Ne)) * N / dN;
         if (!(lo < mn && mn < hi)) mn = 0.5 * (lo + hi);
         spec = false;
       }
@@ -328,7 +355,7 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
   while (!found && it < a.max_newton) {
     ++it;
     if (spec) {
-      FOR_CHUNKS(c) chunk_sums<CACHE, true>(a, c, vls, xls, mu, ikT, fdl, sh);
+      FOR_CHUNKS(c) chunk_sums<CACHE, true>(a, c, vls, xls, mu, ikT, fdl, sh, k_on);
       grid_allreduce(a.part, nchunk, a.res, 0, 8, 0x80u, G, lb, bank, ++nred, a.err, r, sh);
     } else {
       FOR_CHUNKS(c) chunk_sums<CACHE, false>(a, c, vls, xls, mu, ikT, fdl, sh);
@@ -349,7 +376,8 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
       hi = mu;
     else
       lo = mu;
-    double mn = mu - f / dN;
+    // Newton on ln N(mu) = ln N_e (the step of Newton on N near the root)
+    double mn = mu - (log(N) - log(a.Ne)) * N / dN;
     if (!(lo < mn && mn < hi)) mn = 0.5 * (lo + hi);
     if (fabs(mn - mu) <= 1e-15 * (fabs(mu) + kT)) {
       mu = mn;
@@ -362,15 +390,28 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
 
   // 3. active density and the mixing reductions (unless the last pass formed them)
   if (!have_sums) {
-    FOR_CHUNKS(c) chunk_sums<CACHE, true>(a, c, vls, xls, mu, ikT, fdl, sh);
+    FOR_CHUNKS(c) chunk_sums<CACHE, true>(a, c, vls, xls, mu, ikT, fdl, sh, k_on);
     grid_allreduce(a.part, nchunk, a.res, 0, 8, 0x80u, G, lb, bank, ++nred, a.err, r, sh);
     for (int k = 0; k < 6; ++k) D[k] = r[2 + k];
   }
-  const double DD = D[0], NN = D[1], KK = D[2], UU = D[3], NA = D[4], MX = D[5];
+  const double DD = D[0], NN = D[1], NA = D[4], MX = D[5];
+  double KK = D[2], UU = D[3];
   const double res = sqrt(DD / NN);
-  const int t = st->iter;
   // every block reaches the same verdict (the sums are identical in all of them)
   const bool last = res < a.tol || !(res == res) || !found || t + 1 >= a.max_iter;
+  // More's weight switches on at the first iteration past the warm-up where
+  // the active density is close (max |dn|/n_a within the trust bound) or mu
+  // has settled (Sec. 2.5.2)
+  int more = more_on0;
+  if (a.mixing != ARCHE_MIX_FIXED && !more && t >= a.warmup &&
+      (MX <= a.trust || fabs(mu - mu_prev) <= MU_SETTLED * kT))
+    more = 1;
+  if (more && !k_on && a.mixing == ARCHE_MIX_MORE && !last) {
+    FOR_CHUNKS(c) chunk_sums<CACHE, true>(a, c, vls, xls, mu, ikT, fdl, sh, true);
+    grid_allreduce(a.part, nchunk, a.res, 0, 8, 0x80u, G, lb, bank, ++nred, a.err, r, sh);
+    KK = r[4];
+    UU = r[5];
+  }
   if (CACHE && last) {
     FOR_CHUNKS(c) {
       for (int q = 0; q < PPT; ++q) {
@@ -382,10 +423,6 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
 #undef FOR_CHUNKS
 
   if (lb == 0 && threadIdx.x == 0) {
-    int more = st->more_on;
-    if (a.mixing != ARCHE_MIX_FIXED && !more && t >= a.warmup &&
-        (MX <= a.trust || fabs(mu - mu_prev) <= MU_SETTLED * kT))
-      more = 1;
     st->mu = mu;
     st->N = N;
     st->dN = dN;
