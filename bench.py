@@ -63,37 +63,41 @@ def kernel_bytes(name, ng, nh, newton_per_launch):
     raise KeyError(name)
 
 
+def sources_sha256(paths):
+    """SHA-256 of the kernel's source files, in order."""
+    h = hashlib.sha256()
+    for p in paths:
+        h.update(open(os.path.join(ROOT, p), "rb").read())
+    return h.hexdigest()
+
+
+def counter_record(kind, name):
+    """A committed rocprofv3 counter record (profiles/<kind>_<name>.json), or None
+    when absent or taken before the kernel's sources last changed."""
+    path = os.path.join(ROOT, "profiles", "%s_%s.json" % (kind, name))
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+        if sources_sha256(d["sources"]) != d["sources_sha256"]:
+            return None
+        return d
+    except Exception:
+        return None
+
+
 def counter_flops_for(name):
     """FP64 flops per launch from the committed rocprofv3 counter run
     (SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes), or None when absent or stale."""
-    path = os.path.join(ROOT, "profiles", "flops_%s.json" % name)
-    if not os.path.exists(path):
-        return None
-    try:
-        d = json.load(open(path))
-        src = os.path.join(ROOT, d["source"])
-        if hashlib.sha256(open(src, "rb").read()).hexdigest() != d["source_sha256"]:
-            return None
-        return float(d["fp64_flops_per_launch"])
-    except Exception:
-        return None
+    d = counter_record("flops", name)
+    return None if d is None else float(d["fp64_flops_per_launch"])
 
 
 def traffic_for(name):
-    """HBM bytes per launch from committed rocprofv3 counter runs, or None when
-    absent or taken before the kernel's source last changed."""
-    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % name)
-    if not os.path.exists(path):
-        return None
-    try:
-        d = json.load(open(path))
-        src = os.path.join(ROOT, d["source"])
-        h = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        if h != d["source_sha256"]:
-            return None
-        return float(d["bytes_per_launch"])
-    except Exception:
-        return None
+    """HBM bytes per launch from committed rocprofv3 counter runs (FETCH_SIZE and
+    WRITE_SIZE, scaled by a copy of known size), or None when absent or stale."""
+    d = counter_record("traffic", name)
+    return None if d is None else float(d["bytes_per_launch"])
 
 
 def cpu_baseline(w, seconds):

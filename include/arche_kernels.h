@@ -103,7 +103,8 @@ arche_status arche_debug_one_center2(arche_ctx *ctx, const double *pos_host, dou
 enum { ARCHE_PROF_SCF_ACTIVE = 0, ARCHE_PROF_FFT_Z = 1, ARCHE_PROF_FFT_STRIDED = 2 };
 arche_status arche_profile_enable(arche_ctx *ctx, int32_t on);
 arche_status arche_profile_reset(arche_ctx *ctx);
-/* Time one launch in `every` of each kind (1, the default: all of them); the
+/* Time one launch in `every` of each kind (1, the default and what
+ * arche_profile_enable sets: all of them); the
  * launches count of arche_profile_read counts the timed ones.  Sampling keeps
  * the event pairs' idle time out of the launches that are not timed.  EINVAL
  * for every < 1, ESTATE unless profiling is enabled. */

@@ -863,7 +863,10 @@ arche_status arche_profile_enable(arche_ctx* c, int32_t on) {
   if (!c) return ARCHE_EINVAL;
   if (on && !c->prof) c->prof = new (std::nothrow) Profiler();
   if (on && !c->prof) return set_err(c, ARCHE_ENOMEM, "profiler allocation failed");
-  if (on) c->prof->mask = on == 1 ? ~0u : (unsigned)on >> 1;
+  if (on) {
+    c->prof->mask = on == 1 ? ~0u : (unsigned)on >> 1;
+    c->prof->every = 1;  // every launch of the timed kinds until arche_profile_sample
+  }
   if (!on) {
     delete c->prof;
     c->prof = nullptr;
