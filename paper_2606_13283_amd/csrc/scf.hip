@@ -104,7 +104,9 @@ __device__ inline void vxc_group(const double* n, double* v) {
 //   and only More's weight uses it)
 // With CACHE, vls and xls (LDS, [PPT][SCF_THREADS]) hold the block's V_i and
 // v_xc(n_i) from the assembly.
-template <bool CACHE, bool ACTIVE>
+// FULL: every point of the chunk lies in the grid (N_g a multiple of SCF_CHUNK),
+// so the ragged-tail selects fold away.
+template <bool CACHE, bool ACTIVE, bool FULL = false>
 __device__ inline void chunk_sums(const ActiveArgs& a, int64_t c, const double* vls, const double* xls, double mu,
                                   double ikT, const FdLds& fdl, double* sh, bool with_k = true) {
   const bool more = a.mixing == ARCHE_MIX_MORE && with_k;  // secant K and U_xc
@@ -120,7 +122,7 @@ __device__ inline void chunk_sums(const ActiveArgs& a, int64_t c, const double* 
 #pragma unroll
     for (int g = 0; g < PG; ++g) {
       const int64_t i = chunk_point(a, c, q0 + g);
-      ok[g] = i < a.ng;
+      ok[g] = FULL || i < a.ng;
       ip[g] = ok[g] ? i : a.ng - 1;
       const double v = CACHE ? vls[(q0 + g) * SCF_THREADS + threadIdx.x] : a.Vi[ip[g]];
       x[g] = (mu - v) * ikT;
@@ -216,7 +218,7 @@ __device__ inline void chunk_sums(const ActiveArgs& a, int64_t c, const double* 
 // all of them take the same branches.  With CACHE (at most one chunk per block)
 // V_i and v_xc(n_i) stay in LDS between the phases; V_i is stored only by the
 // iteration that ends the solve (the energies of Sec. 2.6 read it).
-template <bool CACHE>
+template <bool CACHE, bool FULL = false>
 __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigned G, const FdLds& fdl, double* sh,
                                        double* r, double* vls, double* xls) {
   ScfState* st = a.st;
@@ -254,7 +256,7 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
 #pragma unroll
       for (int g = 0; g < PG; ++g) {
         const int64_t i = chunk_point(a, c, q0 + g);
-        ok[g] = i < a.ng;
+        ok[g] = FULL || i < a.ng;
         const int64_t ic = ok[g] ? i : a.ng - 1;
         n[g] = a.n_i[ic];
         v[g] = a.Vie[ic] + a.VH[ic];
@@ -355,10 +357,10 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
   while (!found && it < a.max_newton) {
     ++it;
     if (spec) {
-      FOR_CHUNKS(c) chunk_sums<CACHE, true>(a, c, vls, xls, mu, ikT, fdl, sh, k_on);
+      FOR_CHUNKS(c) chunk_sums<CACHE, true, FULL>(a, c, vls, xls, mu, ikT, fdl, sh, k_on);
       grid_allreduce(a.part, nchunk, a.res, 0, 8, 0x80u, G, lb, bank, ++nred, a.err, r, sh);
     } else {
-      FOR_CHUNKS(c) chunk_sums<CACHE, false>(a, c, vls, xls, mu, ikT, fdl, sh);
+      FOR_CHUNKS(c) chunk_sums<CACHE, false, FULL>(a, c, vls, xls, mu, ikT, fdl, sh);
       grid_allreduce(a.part, nchunk, a.res, 0, 2, 0u, G, lb, bank, ++nred, a.err, r, sh);
     }
     N = scale * r[0];
@@ -390,7 +392,7 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
 
   // 3. active density and the mixing reductions (unless the last pass formed them)
   if (!have_sums) {
-    FOR_CHUNKS(c) chunk_sums<CACHE, true>(a, c, vls, xls, mu, ikT, fdl, sh, k_on);
+    FOR_CHUNKS(c) chunk_sums<CACHE, true, FULL>(a, c, vls, xls, mu, ikT, fdl, sh, k_on);
     grid_allreduce(a.part, nchunk, a.res, 0, 8, 0x80u, G, lb, bank, ++nred, a.err, r, sh);
     for (int k = 0; k < 6; ++k) D[k] = r[2 + k];
   }
@@ -407,7 +409,7 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
       (MX <= a.trust || fabs(mu - mu_prev) <= MU_SETTLED * kT))
     more = 1;
   if (more && !k_on && a.mixing == ARCHE_MIX_MORE && !last) {
-    FOR_CHUNKS(c) chunk_sums<CACHE, true>(a, c, vls, xls, mu, ikT, fdl, sh, true);
+    FOR_CHUNKS(c) chunk_sums<CACHE, true, FULL>(a, c, vls, xls, mu, ikT, fdl, sh, true);
     grid_allreduce(a.part, nchunk, a.res, 0, 8, 0x80u, G, lb, bank, ++nred, a.err, r, sh);
     KK = r[4];
     UU = r[5];
@@ -444,7 +446,7 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
 }
 
 // One system: the whole cooperative grid is the group.
-template <bool CACHE>
+template <bool CACHE, bool FULL>
 __global__ void __launch_bounds__(SCF_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) k_scf_active(ActiveArgs a) {
   __shared__ double sh[RED_SH];
   __shared__ double r[8];
@@ -453,7 +455,7 @@ __global__ void __launch_bounds__(SCF_THREADS) __attribute__((amdgpu_waves_per_e
   if (a.st->done) return;
   fd_lds_load(&fdl, a.fdt);
   __syncthreads();
-  scf_active_body<CACHE>(a, blockIdx.x, gridDim.x, fdl, sh, r, vls, xls);
+  scf_active_body<CACHE, FULL>(a, blockIdx.x, gridDim.x, fdl, sh, r, vls, xls);
 }
 
 // Many systems in one cooperative launch: system s owns blocks
@@ -848,11 +850,13 @@ int scf_coop_blocks(int64_t ng) {
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  int per_cu = 0, per_cu2 = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_scf_active<true>, SCF_THREADS, 0) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu2, k_scf_active<false>, SCF_THREADS, 0) != hipSuccess)
-    return 0;
-  per_cu = std::min(per_cu, per_cu2);
+  int per_cu = 1 << 20;
+  for (const void* k : {(const void*)k_scf_active<true, false>, (const void*)k_scf_active<false, false>,
+                        (const void*)k_scf_active<true, true>, (const void*)k_scf_active<false, true>}) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, SCF_THREADS, 0) != hipSuccess) return 0;
+    per_cu = std::min(per_cu, n);
+  }
   int64_t b = std::min<int64_t>((int64_t)per_cu * cus, 2 * (int64_t)cus);
   b = std::min<int64_t>(b, (ng + 4 * ARCHE_BLOCK - 1) / (4 * ARCHE_BLOCK));
   return (int)std::max<int64_t>(b, 1);
@@ -1100,15 +1104,13 @@ hipError_t scf_iteration(arche_ctx* c) {
     // dispatched), and a plain launch saves the ~20 us a cooperative launch
     // spends around the kernel.  Waits are bounded in any case (a time-out
     // raises the error flag instead of hanging).
+    const bool full = c->active.ng % SCF_CHUNK == 0;
+    const void* kern = cache ? (full ? (const void*)k_scf_active<true, true> : (const void*)k_scf_active<true, false>)
+                             : (full ? (const void*)k_scf_active<false, true> : (const void*)k_scf_active<false, false>);
     if (scf_plain_launch(c)) {
-      if (cache)
-        hipLaunchKernelGGL(k_scf_active<true>, dim3(c->coop_blocks), dim3(SCF_THREADS), 0, c->stream, c->active);
-      else
-        hipLaunchKernelGGL(k_scf_active<false>, dim3(c->coop_blocks), dim3(SCF_THREADS), 0, c->stream, c->active);
-      HIP_TRY(hipGetLastError());
+      HIP_TRY(hipLaunchKernel(kern, dim3(c->coop_blocks), dim3(SCF_THREADS), args, 0, c->stream));
     } else {
-      HIP_TRY(hipLaunchCooperativeKernel(cache ? (const void*)k_scf_active<true> : (const void*)k_scf_active<false>,
-                                         dim3(c->coop_blocks), dim3(SCF_THREADS), args, 0, c->stream));
+      HIP_TRY(hipLaunchCooperativeKernel(kern, dim3(c->coop_blocks), dim3(SCF_THREADS), args, 0, c->stream));
     }
   }
   if (!c->fused) return scf_iteration_rest_plain(c);
