@@ -10,13 +10,15 @@ positions and Maxwell-Boltzmann velocities.
 A step is one MD step: structure factor and ionic field, one-center guess,
 the SCF to convergence, free energy and pressure, forces, Verlet update.
 Prints one JSON line.  The value is SCF iterations per second over the timed
-steps; the wall time per MD step is ms_per_step.  Two more comparisons ride
-along (untimed for `value`): "batch" (64 independent 108-atom snapshots solved
-one after another vs in one batch) and "learned_init" (plain guess vs previous
-density vs the learned proposal on 256-atom MD at 64^3).
+steps; the wall time per MD step is ms_per_step.  More comparisons ride along
+(untimed for `value`): "batch" (64 independent 108-atom snapshots solved one
+after another vs in one batch), "learned_init" and "learned_init_128" (plain
+guess vs previous density vs the learned proposal on 256-atom MD at 64^3 and on
+the benchmark's own 1024-atom cell at 128^3), "ablation" (the setups of the
+paper's SCF-count comparison) and "large_snapshot" (4000 atoms at 192^3).
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--batch N] [--learned K]
-                  [--no-cpu-baseline] [--copy-probe MIB]
+                  [--ablation K] [--large 0|1] [--no-cpu-baseline] [--copy-probe MIB]
 """
 from __future__ import annotations
 
@@ -186,13 +188,16 @@ def bench_batch(count):
             "bit_identical_to_sequential": bool(same), "schedule": info2, "tuning": info1}
 
 
-def bench_learned(steps_train, epochs, steps_eval):
-    """The learned initial density on 256 Al atoms at 64^3: training samples from
-    plain MD at 2, 4, 6, 8, 10 eV (`steps_train` steps each), `epochs` of Adam on
-    the GPU, then a held-out 5 eV trajectory of `steps_eval` MD steps solved
-    from the plain guess, from the previous converged density alone and from
-    the learned proposal at the same positions.  Wall time per MD step and SCF
-    iterations of each, the free energies agreeing to 1e-9."""
+def bench_learned(steps_train, epochs, steps_eval, size=64):
+    """The learned initial density.  size 64: 256 Al atoms at 64^3, training
+    samples from plain MD at 2, 4, 6, 8, 10 eV (`steps_train` steps each), a
+    held-out 5 eV trajectory.  size 128: the 1024-atom, 128^3, 10 eV cell,
+    samples from three other seeded cells (`steps_train` steps each), the
+    benchmark's own trajectory held out.  `epochs` of Adam on the GPU, then
+    `steps_eval` MD steps solved from the plain guess, from the previous
+    converged density alone and from the learned proposal at the same positions.
+    Wall time per MD step and SCF iterations of each, the free energies
+    agreeing to 1e-9."""
     import numpy as np
     import torch
 
@@ -200,11 +205,18 @@ def bench_learned(steps_train, epochs, steps_eval):
     from paper_2606_13283_amd import learned as LN
     from paper_2606_13283_amd import workloads as W
 
-    ws = [W.fcc256_at(T, seed=100 + i) for i, T in enumerate((2.0, 4.0, 6.0, 8.0, 10.0))]
+    if size == 64:
+        ws = [W.fcc256_at(T, seed=100 + i) for i, T in enumerate((2.0, 4.0, 6.0, 8.0, 10.0))]
+        w = W.fcc256_at(5.0, seed=300)
+        desc = "fcc256_64^3 MD at 5 eV (held out), trained on 2-10 eV"
+    else:
+        ws = [W.rand1024(seed=101 + i) for i in range(3)]
+        w = W.rand1024()
+        desc = "rand1024_128^3_10eV MD (the benchmark's trajectory, held out), trained on three other seeded cells"
     t0 = time.perf_counter()
     samples = LN.generate(ws, steps=steps_train)
     t_gen = time.perf_counter() - t0
-    net = arche.Net((64, 64, 64))
+    net = arche.Net(w.grid)
     net.set_params(LN.init_params(0))
     data = [s for s, _ in samples]
     n0s = [LN.n0_of(ws[0])] * len(data)
@@ -214,7 +226,6 @@ def bench_learned(steps_train, epochs, steps_eval):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     n_train_steps = epochs * len(data)
-    w = W.fcc256_at(5.0, seed=300)
     # one variant at a time, each with only its own context alive, at the positions
     # of the plain trajectory (several live contexts make one of them run slower)
     kinds = {"plain": arche.INIT_ONE_CENTER, "previous_density": arche.INIT_KEEP, "learned": arche.INIT_LEARNED}
@@ -243,14 +254,15 @@ def bench_learned(steps_train, epochs, steps_eval):
         tr.close()
     net.close()
     same = all(abs(a - b) <= 1e-9 * abs(a) for k in ("previous_density", "learned") for a, b in zip(Fs["plain"], Fs[k]))
-    print("[bench] learned: iterations plain %.1f, previous density %.1f, learned %.1f" % tuple(
-        float(np.mean(iters[k])) for k in ("plain", "previous_density", "learned")), file=sys.stderr, flush=True)
-    return {"workload": "fcc256_64^3 MD at 5 eV (held out), trained on 2-10 eV", "samples": len(data),
+    print("[bench] learned %d^3: iterations plain %.1f, previous density %.1f, learned %.1f" % ((size,) + tuple(
+        float(np.mean(iters[k])) for k in ("plain", "previous_density", "learned"))), file=sys.stderr, flush=True)
+    return {"workload": desc, "samples": len(data),
             "epochs": epochs, "sample_generation_s": t_gen, "training_s": t_train,
             "training_steps_per_s": n_train_steps / t_train, "loss_first_last_epoch": [hist[0], hist[-1]],
             "md_steps": steps_eval,
             "wall_s_per_md_step": {k: wall[k] / steps_eval for k in wall},
             "scf_iters_per_md_step": {k: float(np.mean(iters[k])) for k in iters},
+            "wall_reduction_vs_plain": {k: 1.0 - wall[k] / wall["plain"] for k in ("previous_density", "learned")},
             "scf_iters_each_step": iters, "free_energy_agrees_1e-9": bool(same)}
 
 
@@ -510,6 +522,7 @@ def main():
         out["batch"] = bench_batch(args.batch)
     if args.learned > 0:
         out["learned_init"] = bench_learned(16, 12, args.learned)
+        out["learned_init_128"] = bench_learned(6, 6, min(args.learned, 4), size=128)
     if args.ablation > 0:
         out["ablation"] = bench_ablation(args.ablation)
     if args.large > 0:
