@@ -34,9 +34,8 @@ double fd_host(int j, double x) {
     double p = (j == 0) ? 2.0 * r : (j == 1) ? x * r * (2.0 / 3.0) : x * x * r * 0.4;
     return p * std::fma(u, s, 1.0);
   }
-  int i = (int)std::floor(x - FD_X_LO);
-  i = std::max(0, std::min(FD_NINT - 1, i));
-  double t = 2.0 * (x - (FD_X_LO + i)) - 1.0;
+  int i;
+  const double t = fd_locate(x, i);
   double s = FD_POLY[j][i][FD_NCOEF - 1];
   for (int k = FD_NCOEF - 2; k >= 0; --k) s = std::fma(s, t, FD_POLY[j][i][k]);
   return s;
