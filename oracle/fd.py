@@ -59,18 +59,24 @@ def I_p12_inverse_array(y, x0=None):
     lo = np.log(y / math.gamma(1.5)) - 1e-9
     hi = np.maximum((1.5 * y) ** (2.0 / 3.0), lo + 1.0) + 1.0
     x = 0.5 * (lo + hi) if x0 is None else np.clip(np.asarray(x0, dtype=np.float64), lo, hi)
-    done = np.zeros(y.shape, dtype=bool)
+    x = np.array(x, dtype=np.float64).reshape(y.shape)
+    lo = np.broadcast_to(lo, y.shape).copy()
+    hi = np.broadcast_to(hi, y.shape).copy()
+    # each element iterates on its own; only the unfinished ones are evaluated
+    act = np.flatnonzero(np.ones(y.shape, dtype=bool))
+    xf, lof, hif, yf = x.reshape(-1), lo.reshape(-1), hi.reshape(-1), y.reshape(-1)
     for _ in range(200):
-        v = fd_integrals(x, ("m12", "p12"))
-        f = v["p12"] - y
-        hi = np.where(~done & (f > 0), x, hi)
-        lo = np.where(~done & (f <= 0), x, lo)
-        xn = x - f / (0.5 * v["m12"])
-        xn = np.where((lo < xn) & (xn < hi), xn, 0.5 * (lo + hi))
-        fin = np.abs(xn - x) <= 2e-16 * np.maximum(1.0, np.abs(x))
-        x = np.where(done, x, xn)
-        done |= fin
-        if done.all():
+        xa = xf[act]
+        v = fd_integrals(xa, ("m12", "p12"))
+        f = v["p12"] - yf[act]
+        hia = np.where(f > 0, xa, hif[act])
+        loa = np.where(f <= 0, xa, lof[act])
+        xn = xa - f / (0.5 * v["m12"])
+        xn = np.where((loa < xn) & (xn < hia), xn, 0.5 * (loa + hia))
+        fin = np.abs(xn - xa) <= 2e-16 * np.maximum(1.0, np.abs(xa))
+        xf[act], lof[act], hif[act] = xn, loa, hia
+        act = act[~fin]
+        if act.size == 0:
             return x
     raise RuntimeError("I_{1/2}^{-1} did not converge")
 

@@ -42,11 +42,16 @@ class StepResult:
 
 
 def solve_at(sys, init="uniform", prev=None, mixing="more", tol=1e-10, mu0=None,
-             max_iter=2000) -> StepResult:
-    """Structure factor -> V^ie -> initial density -> SCF -> F, P, forces."""
+             max_iter=2000, solver="paper") -> StepResult:
+    """Structure factor -> V^ie -> initial density -> SCF -> F, P, forces.
+    solver "paper": the iteration of Sec. 2.5 (`scf`); "anderson": the same
+    fixed point by `scf_anderson` (for tests that only need the solution)."""
     ion = scf_mod.ionic_setup(sys)
     n0, fb = scf_mod.initial_density(sys, ion, init, prev)
-    res = scf_mod.scf(sys, ion, n0, mixing=mixing, tol=tol, mu0=mu0, max_iter=max_iter)
+    if solver == "anderson":
+        res = scf_mod.scf_anderson(sys, ion, n0, tol=tol, max_iter=max_iter, beta=0.3, mu0=mu0)
+    else:
+        res = scf_mod.scf(sys, ion, n0, mixing=mixing, tol=tol, mu0=mu0, max_iter=max_iter)
     res.used_fallback = fb
     th = thermo.evaluate(sys, ion, res)
     return StepResult(sys, ion, res, th, sys.grid.forward(res.n))

@@ -83,7 +83,7 @@ def tab_base():
     tab = ionic.Tabulated(smeared_core(3.0, 1.1, 0.45, dq, n), dq)
     s = scf.System((L, L, L), (16, 16, 16), pos, np.zeros(4, int), (3.0,), (tab,), (W.AL_MASS,), W.ev(10.0),
                    0.2, True)
-    return s, md.solve_at(s, tol=TOL)
+    return s, md.solve_at(s, tol=TOL, solver="anderson")
 
 
 def _F_at(s, prev_n, pos=None, cell=None):
@@ -91,7 +91,9 @@ def _F_at(s, prev_n, pos=None, cell=None):
         s = scf.System(cell, s.shape, pos, s.species, s.Z, s.rc, s.mass, s.kT, s.lam, s.xc)
     elif pos is not None:
         s = s.with_positions(pos)
-    r = md.solve_at(s, init="given", prev=prev_n, tol=TOL)
+    # the solution alone is needed: Anderson's acceleration reaches the same
+    # fixed point (test_one_fixed_point_for_all_algorithms) in fewer iterations
+    r = md.solve_at(s, init="given", prev=prev_n, tol=TOL, solver="anderson")
     assert r.scf.converged
     return r.th.F
 

@@ -24,8 +24,10 @@ def small_system(T_ev=10.0, seed=11, n_atoms=4, N=16, lam=0.2, xc=True):
 
 @pytest.fixture(scope="module")
 def base():
+    # the fixed point itself; the paper's iteration from the uniform density
+    # reaches it too (test_one_fixed_point_for_all_algorithms)
     s = small_system()
-    return s, md.solve_at(s, tol=TOL)
+    return s, md.solve_at(s, tol=TOL, solver="anderson")
 
 
 def test_charge_conservation(base):
@@ -59,17 +61,18 @@ def test_more_weight_closed_form():
 
 
 def test_one_fixed_point_for_all_algorithms(base):
-    s, r = base
+    s, r = base  # r: Anderson's acceleration from the uniform density
     ion = r.ion
-    rf = scf.scf(s, ion, scf.initial_density(s, ion)[0], mixing="fixed", w_fixed=0.9, tol=TOL)
+    # the paper's iteration (Sec. 2.5, More's weight) from the uniform density
+    rp = scf.scf(s, ion, scf.initial_density(s, ion)[0], mixing="more", tol=TOL)
+    assert r.scf.iters < rp.iters
     pert = r.scf.n * (1 + 0.05 * np.cos(2 * math.pi * s.grid.points()[..., 1] / s.cell[1]))
     pert *= s.Ne / s.grid.integrate(pert)
-    rg = scf.scf(s, ion, pert, mixing="more", tol=TOL)
-    # Anderson's acceleration (the generic iteration behind the stored values
-    # of the large cells) reaches the same fixed point
-    ra = scf.scf_anderson(s, ion, scf.initial_density(s, ion)[0], tol=TOL, beta=0.3)
-    assert ra.iters < r.scf.iters
-    for other in (rf, rg, ra):
+    # fixed mixing and More's weight from a perturbed density (a residual of
+    # 1e-11 leaves F within 1e-20, P and forces within 1e-11)
+    rf = scf.scf(s, ion, pert, mixing="fixed", w_fixed=0.9, tol=1e-11)
+    rg = scf.scf(s, ion, pert, mixing="more", tol=1e-11)
+    for other in (rp, rf, rg):
         assert other.converged
         th = thermo.evaluate(s, ion, other)
         assert abs(th.F - r.th.F) <= 1e-12 * abs(r.th.F)
@@ -82,7 +85,9 @@ def _F_at(s, prev_n, pos=None, cell=None):
         s = scf.System(cell, s.shape, pos, s.species, s.Z, s.rc, s.mass, s.kT, s.lam, s.xc)
     elif pos is not None:
         s = s.with_positions(pos)
-    r = md.solve_at(s, init="given", prev=prev_n, tol=TOL)
+    # the solution alone is needed: Anderson's acceleration reaches the same
+    # fixed point (test_one_fixed_point_for_all_algorithms) in fewer iterations
+    r = md.solve_at(s, init="given", prev=prev_n, tol=TOL, solver="anderson")
     assert r.scf.converged
     return r.th.F
 
@@ -114,7 +119,7 @@ def test_pressure_is_minus_volume_derivative(base):
 def test_translation_by_grid_vector(base):
     s, r = base
     shift = np.array([3, 5, 14]) * np.array(s.cell) / np.array(s.shape)
-    r2 = md.solve_at(s.with_positions(s.pos + shift), tol=TOL)
+    r2 = md.solve_at(s.with_positions(s.pos + shift), tol=TOL, solver="anderson")
     assert abs(r2.th.F - r.th.F) <= 1e-12 * abs(r.th.F)
     assert abs(r2.th.P - r.th.P) <= 1e-11 * abs(r.th.P)
     assert np.max(np.abs(r2.th.forces - r.th.forces)) <= 1e-9
@@ -127,7 +132,7 @@ def test_perfect_fcc_on_grid_has_zero_forces():
     pos = W.fcc_positions(2, L)
     s = scf.System((L, L, L), (16, 16, 16), pos, np.zeros(32, int), (3.0,), (1.1,), (W.AL_MASS,),
                    W.ev(10.0), 0.2, True)
-    r = md.solve_at(s, tol=TOL)
+    r = md.solve_at(s, tol=TOL, solver="anderson")
     assert r.scf.converged
     # inversion symmetry about every atom: the electron-ion and reciprocal Ewald forces vanish
     assert np.max(np.abs(r.th.force_terms["F_ie"])) <= 1e-10
