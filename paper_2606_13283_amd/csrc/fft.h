@@ -70,6 +70,9 @@ struct FftFuse {
 };
 // k-vector helpers of the x pass: element k of column `line` in the tile at outer
 // index o (the y index) is the point (m_x = k, m_y = o, m_z = c0 + line).
+// x passes tile the whole (y, k_z) plane of an x index as one run of N_y N_h
+// columns (col = m_y N_h + m_z), so that a tile of TK columns is one contiguous
+// 16 TK-byte run of every x plane, aligned as the plane is.
 struct XGeom {
   int Nx, Ny, Nz;
   double Lx, Ly, Lz;
@@ -79,7 +82,14 @@ struct XGeom {
     const double kz = (double)mz / Lz;
     return kx * kx + ky * ky + kz * kz;
   }
+  // |k|^2 at x index mx and plane column col
+  __device__ double k2c(int mx, int col) const {
+    const int nh = Nz / 2 + 1;
+    const int my = col / nh;
+    return k2(mx, my, col - my * nh);
+  }
   __device__ double weight(int mz) const { return (mz == 0 || 2 * mz == Nz) ? 1.0 : 2.0; }
+  __device__ double weightc(int col) const { return weight(col % (Nz / 2 + 1)); }
 };
 
 // Arguments of one strided pass (lines along y or x of the half spectrum).
@@ -88,7 +98,8 @@ struct StridedArgs {
   const cplx* src;   // MODE 3: the input spectrum
   const cplx* tw;    // [L] exp(-2 pi i m / L)
   int64_t es, os;    // element stride along the line, stride between outer indices
-  int ncols, nchunk; // columns (k_z values) per outer index, tiles of TK columns
+  int ncols, nchunk; // columns per outer index (y passes: k_z values; x passes: the
+                     // whole (y, k_z) plane, one outer index), tiles of TK columns
   double scale;
   FftFuse f;
   XGeom g;

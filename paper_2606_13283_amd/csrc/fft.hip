@@ -601,19 +601,20 @@ hipError_t strided_pass(const FftPlan* p, cplx* data, int axis, int sign, double
     es = Nh;
     os = (int64_t)Ny * Nh;
     nouter = Nx;
-  } else {  // axis 0: lines along x, element stride Ny*Nh, one outer index per y
+  } else {  // axis 0: lines along x, element stride Ny*Nh, the (y, k_z) plane as one run of columns
     es = (int64_t)Ny * Nh;
-    os = Nh;
-    nouter = Ny;
+    os = 0;
+    nouter = 1;
   }
+  const int ncols = axis == 1 ? Nh : Ny * Nh;
   ProfScope prof(PROF_FFT_STRIDED, s);
   if (ct_supported(ax.L))
-    return ct_strided(ax.L, 0, sign, data, data, ax.tw, es, os, nouter, Nh, scale, FftFuse{}, XGeom{}, axis, s);
+    return ct_strided(ax.L, 0, sign, data, data, ax.tw, es, os, nouter, ncols, scale, FftFuse{}, XGeom{}, axis, s);
   const int TK = strided_tile(ax.L);
-  const int nchunk = (Nh + TK - 1) / TK;
+  const int nchunk = (ncols + TK - 1) / TK;
   const size_t lds = (size_t)(2 * ax.L * TK + ax.L) * sizeof(cplx);
   hipLaunchKernelGGL(k_fft_strided, dim3(nouter * nchunk), dim3(ARCHE_BLOCK), lds, s, data, ax.tw, ax.L,
-                     es, os, Nh, TK, nchunk, radices_of(ax), sign, scale);
+                     es, os, ncols, TK, nchunk, radices_of(ax), sign, scale);
   return hipGetLastError();
 }
 
@@ -774,7 +775,7 @@ bool fft_fusable(const FftPlan* p) {
 }
 int fft_x_blocks(const FftPlan* p) {
   const int tk = kStridedTK[p->N[0] <= 1024 ? g_tile_var[1][p->N[0]] : 0];
-  return p->N[1] * ((p->Nh + tk - 1) / tk);
+  return (p->N[1] * p->Nh + tk - 1) / tk;
 }
 bool fft_x_roundtrip(int L) { return L == 128; }  // plane_len
 bool fft_plane_fusable(const FftPlan* p) {
@@ -805,8 +806,8 @@ bool fft_r2c_passes(const FftPlan* p, const double* in, cplx* out, double in_sca
                         XGeom{}, 1);
   }
   const int mode = fout == R2C_OUT_LAP ? 1 : (fout == R2C_OUT_UH ? 2 : 0);
-  o[2] = strided_desc(p->N[0], mode, -1, out, out, p->ax[0].tw, (int64_t)p->N[1] * Nh, Nh, p->N[1], Nh, out_scale, f,
-                      xgeom(p, f), 0);
+  o[2] = strided_desc(p->N[0], mode, -1, out, out, p->ax[0].tw, (int64_t)p->N[1] * Nh, 0, 1, p->N[1] * Nh, out_scale,
+                      f, xgeom(p, f), 0);
   return true;
 }
 
@@ -816,7 +817,7 @@ bool fft_c2r_passes(const FftPlan* p, const cplx* in, cplx* work, double* out, d
   const int64_t npairs = (int64_t)p->N[0] * p->N[1] / 2;
   const int Nh = p->Nh;
   o[0] = strided_desc(p->N[0], fin == C2R_IN_MIX ? 3 : 0, +1, work, fin == C2R_IN_MIX ? in : work, p->ax[0].tw,
-                      (int64_t)p->N[1] * Nh, Nh, p->N[1], Nh, 1.0, f, xgeom(p, f), 0);
+                      (int64_t)p->N[1] * Nh, 0, 1, p->N[1] * Nh, 1.0, f, xgeom(p, f), 0);
   if (fft_plane_fusable(p)) {
     o[1] = nop_desc();
     o[2] = plane_desc(FFT_PASS_YZ_C2R, p->N[2], fout, work, out, p->ax[2].tw, p->N[0], 1.0, out_scale, f);
@@ -914,8 +915,8 @@ hipError_t fft_tune(const FftPlan* p, cplx* scratch_c, double* scratch_r, hipStr
         ps = strided_desc(L, 0, -1, scratch_c, scratch_c, p->ax[1].tw, Nh, (int64_t)p->N[1] * Nh, p->N[0], Nh, 1.0,
                           FftFuse{}, XGeom{}, 1);
       else if (pass == 1)
-        ps = strided_desc(L, 0, -1, scratch_c, scratch_c, p->ax[0].tw, (int64_t)p->N[1] * Nh, Nh, p->N[1], Nh, 1.0,
-                          FftFuse{}, XGeom{}, 0);
+        ps = strided_desc(L, 0, -1, scratch_c, scratch_c, p->ax[0].tw, (int64_t)p->N[1] * Nh, 0, 1, p->N[1] * Nh,
+                          1.0, FftFuse{}, XGeom{}, 0);
       else
         ps = z_desc(FFT_PASS_Z_R2C, L, 0, scratch_r, scratch_c, p->ax[2].tw, npairs, 1.0, 1.0, FftFuse{});
       for (int w = 0; w < 2 && e == hipSuccess; ++w) e = launch_pass_any(ps, s);

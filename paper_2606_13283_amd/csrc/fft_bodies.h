@@ -35,7 +35,7 @@ struct ColOutLap {  // R2C_OUT_LAP
   int o, c0;
   __device__ void operator()(int line, int k, cplx v) const {
     if (line >= nc) return;
-    const double q2 = 39.478417604357434 * g.k2(k, o, c0 + line);  // (2 pi)^2 |k|^2
+    const double q2 = 39.478417604357434 * g.k2c(k, c0 + line);  // (2 pi)^2 |k|^2
     base[(int64_t)k * es + line] = cscale(v, -q2 * scale);
   }
   __device__ void barrier_before() const {}
@@ -56,10 +56,10 @@ struct ColOutUH {  // R2C_OUT_UH
     const int64_t at = (int64_t)k * es + line;
     const cplx a = cscale(v, scale);
     base[at] = a;
-    const double k2 = g.k2(k, o, c0 + line);
+    const double k2 = g.k2c(k, c0 + line);
     if (k2 > 0.0) {
       const cplx d = csub(nhat_i[at], a);
-      *acc += g.weight(c0 + line) * (d.x * d.x + d.y * d.y) / (3.14159265358979323846 * k2);
+      *acc += g.weightc(c0 + line) * (d.x * d.x + d.y * d.y) / (3.14159265358979323846 * k2);
     }
   }
   __device__ void barrier_before() const {}
@@ -80,7 +80,7 @@ struct ColInMix {  // C2R_IN_MIX: n_o^ = a + w (nhat_i - a); nhat_i <- n_o^; val
     const cplx x = a[at];
     const cplx no = cadd(x, cscale(csub(nhat_i[at], x), w));
     nhat_i[at] = no;
-    const double k2 = g.k2(k, o, c0 + line);
+    const double k2 = g.k2c(k, c0 + line);
     return k2 > 0.0 ? cscale(no, 1.0 / (3.14159265358979323846 * k2)) : cplx{0.0, 0.0};
   }
 };
@@ -91,7 +91,7 @@ struct LdsLap {  // MODE 4: the forward result times -(2 pi |k|)^2 scale, back i
   XGeom g;
   int o, c0, TK;
   __device__ void operator()(int line, int k, cplx v) const {
-    const double q2 = 39.478417604357434 * g.k2(k, o, c0 + line);  // (2 pi)^2 |k|^2
+    const double q2 = 39.478417604357434 * g.k2c(k, c0 + line);  // (2 pi)^2 |k|^2
     buf[k * TK + line] = cscale(v, -q2 * scale);
   }
   __device__ void barrier_before() const { __syncthreads(); }
