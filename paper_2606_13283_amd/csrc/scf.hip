@@ -219,7 +219,7 @@ __device__ inline void chunk_sums(const ActiveArgs& a, int64_t c, const double* 
 // V_i and v_xc(n_i) stay in LDS between the phases; V_i is stored only by the
 // iteration that ends the solve (the energies of Sec. 2.6 read it).
 template <bool CACHE, bool FULL = false>
-__device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigned G, const FdLds& fdl, double* sh,
+__device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigned G, FdLds& fdl, double* sh,
                                        double* r, double* vls, double* xls) {
   ScfState* st = a.st;
   // the state as the launch found it, read before the first all-reduce: block 0
@@ -246,22 +246,40 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
 #define FOR_CHUNKS(c)                                           \
   for (int64_t c = lb; c < nchunk; c += (CACHE ? nchunk : G))
 
-  // 1. potential assembly (+ the Taylor sums of N at the previous mu)
+  // 1. potential assembly (+ the Taylor sums of N at the previous mu).  Each
+  // group's loads are issued a group ahead, so they are in flight while the
+  // previous group is evaluated; the first group's overlap the load of the
+  // I_{1/2} table into LDS.
+  double pn[PG], pe[PG], ph[PG], pl[PG];
+  auto fetch = [&](int64_t c, int q0) {
+#pragma unroll
+    for (int g = 0; g < PG; ++g) {
+      const int64_t i = chunk_point(a, c, q0 + g);
+      const int64_t ic = (FULL || i < a.ng) ? i : a.ng - 1;
+      pn[g] = a.n_i[ic];
+      pe[g] = a.Vie[ic];
+      ph[g] = a.VH[ic];
+      pl[g] = a.lap_i[ic];
+    }
+  };
+  if ((int64_t)lb < nchunk) fetch(lb, 0);
+  fd_lds_load(&fdl, a.fdt);
+  __syncthreads();
   FOR_CHUNKS(c) {
     double acc[7] = {0.0, -INFINITY, -INFINITY, 0.0, 0.0, 0.0, 0.0};
+    if (c != (int64_t)lb) fetch(c, 0);
 #pragma unroll 1
   for (int q0 = 0; q0 < PPT; q0 += PG) {
       bool ok[PG];
       double n[PG], v[PG], lp[PG], vx[PG];
 #pragma unroll
       for (int g = 0; g < PG; ++g) {
-        const int64_t i = chunk_point(a, c, q0 + g);
-        ok[g] = FULL || i < a.ng;
-        const int64_t ic = ok[g] ? i : a.ng - 1;
-        n[g] = a.n_i[ic];
-        v[g] = a.Vie[ic] + a.VH[ic];
-        lp[g] = a.lap_i[ic];
+        ok[g] = FULL || chunk_point(a, c, q0 + g) < a.ng;
+        n[g] = pn[g];
+        v[g] = pe[g] + ph[g];
+        lp[g] = pl[g];
       }
+      if (q0 + PG < PPT) fetch(c, q0 + PG);
       if (a.xc) {
         vxc_group(n, vx);
       } else {
@@ -453,8 +471,6 @@ __global__ void __launch_bounds__(SCF_THREADS) __attribute__((amdgpu_waves_per_e
   __shared__ FdLds fdl;
   __shared__ double vls[CACHE ? PPT * SCF_THREADS : 1], xls[CACHE ? PPT * SCF_THREADS : 1];
   if (a.st->done) return;
-  fd_lds_load(&fdl, a.fdt);
-  __syncthreads();
   scf_active_body<CACHE, FULL>(a, blockIdx.x, gridDim.x, fdl, sh, r, vls, xls);
 }
 
@@ -470,8 +486,6 @@ k_scf_active_batch(const ActiveArgs* __restrict__ args, const int* __restrict__ 
   while (s + 1 < nsys && group_begin[s + 1] <= (int)blockIdx.x) ++s;
   const ActiveArgs a = args[s];
   if (a.st->done) return;
-  fd_lds_load(&fdl, a.fdt);
-  __syncthreads();
   const unsigned lb = blockIdx.x - group_begin[s];
   const unsigned G = group_begin[s + 1] - group_begin[s];
   if ((int64_t)G >= a.nchunk)
