@@ -289,7 +289,7 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
 #pragma unroll
       for (int g = 0; g < PG; ++g) {
         v[g] += vx[g];
-        if (a.lam != 0.0) v[g] += -0.5 * a.lam * lp[g] / sqrt(n[g]);
+        if (a.lam != 0.0) v[g] += -0.5 * a.lam * lp[g] * rsqrt_nr(n[g]);
         if (CACHE) {
           vls[(q0 + g) * SCF_THREADS + threadIdx.x] = v[g];
           xls[(q0 + g) * SCF_THREADS + threadIdx.x] = vx[g];
