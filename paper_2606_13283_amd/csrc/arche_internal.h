@@ -19,7 +19,7 @@ struct ScfState {
   double mu, N, dN;
   double res;      // ||n_i - n_a|| / ||n_a||
   double K;        // int dn^2 / (dn_a/dmu)
-  double Uxc;      // int (v_xc(n_i) - v_xc(n_a)) dn
+  double Uxc;      // int (v_xc(n_i) - v_xc(n_a)) dn [+ int v_vW[n_i] dn when uvw_w is set]
   double Uvw;      // int (v_vW[n_i] - v_vW[n_a]) dn
   double UH;       // 1/|Omega| sum |dn^|^2 / (pi k^2)
   double w;        // mixing weight of the last iteration
@@ -99,6 +99,10 @@ struct ActiveArgs {
   double trust;
   int max_newton;
   int max_iter;  // the iteration that reaches it is the last (done is raised)
+  // with More's secant weight and vW: (n_i - n_a)/sqrt(n_a) out, for the pass that
+  // sums the v_vW[n_a] part of U_vW, and the v_vW[n_i] part summed with U_xc
+  // (null: the U_vW pass does both)
+  double* uvw_w;
 };
 
 // The rest of an iteration is a fixed sequence of steps; a step that does not

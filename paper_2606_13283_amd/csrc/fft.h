@@ -62,6 +62,8 @@ struct FftFuse {
   double* n_i;           // R2C_IN_MIX_SQRT, C2R_OUT_UVW
   const double* n_a;     // C2R_OUT_UVW
   const double* lap_i;   // C2R_OUT_UVW
+  const double* uvw_w;   // C2R_OUT_UVW: (n_i - n_a)/sqrt(n_a) from the SCF kernel, which has summed the
+                         // v_vW[n_i] part of U_vW (null: the pass forms all of U_vW from n_i, n_a, lap_i)
   cplx* nhat_i;          // R2C_OUT_UH (read), C2R_IN_MIX (read/write)
   double* partials;      // one double per block of the fused pass
   double lam;            // C2R_OUT_UVW

@@ -261,10 +261,15 @@ struct PairOutUvw {  // C2R_OUT_UVW: accumulate (v_vW[n_i] - v_vW[n_a]) (n_i - n
   const double* ni;
   const double* lapi;
   const double* na;
+  const double* w;  // (n_i - n_a)/sqrt(n_a) with the v_vW[n_i] part summed elsewhere, or null
   int L, nv;
   double scale, hl;  // hl = lambda/2
   double* acc;
   __device__ void one(int64_t at, double lap) const {
+    if (w) {
+      *acc += hl * lap * w[at];
+      return;
+    }
     const double a = ni[at], b = na[at];
     const double vi = -hl * lapi[at] / sqrt(a);
     const double va = -hl * lap / sqrt(b);
@@ -297,7 +302,8 @@ __device__ inline void z_c2r_body(const ZArgs& A, unsigned bid, cplx* lds, cplx*
     const int64_t off = p0 * 2 * L;
     run<L, B, NT, false, +1, 1>(
         HermIn{in + p0 * 2 * Nh, L, Nh, nb},
-        PairOutUvw{A.f.n_i + off, A.f.lap_i + off, A.f.n_a + off, L, nb, A.out_scale, 0.5 * A.f.lam, &acc}, lds, tw,
+        PairOutUvw{A.f.n_i + off, A.f.lap_i + off, A.f.n_a + off, A.f.uvw_w ? A.f.uvw_w + off : nullptr, L, nb,
+                   A.out_scale, 0.5 * A.f.lam, &acc}, lds, tw,
         nb, typename Plan<L>::R{});
     acc = block_sum(acc, sh);
     if (threadIdx.x == 0) A.f.partials[bid] = acc;
@@ -457,17 +463,29 @@ __device__ inline void yz_c2r_body(const ZArgs& A, unsigned bid, cplx* plane, cp
       out2[q] = double2{rl[at], rl[at + 1]};
     }
   } else {
-    // (v_vW[n_i] - v_vW[n_a]) (n_i - n_a) with v_vW[n] = -(lambda/2) lap / sqrt(n)
-    const double2* ni2 = (const double2*)(A.f.n_i + off);
-    const double2* li2 = (const double2*)(A.f.lap_i + off);
-    const double2* na2 = (const double2*)(A.f.n_a + off);
+    // (v_vW[n_i] - v_vW[n_a]) (n_i - n_a) with v_vW[n] = -(lambda/2) lap / sqrt(n);
+    // with uvw_w the SCF kernel has summed the v_vW[n_i] part and left
+    // (n_i - n_a)/sqrt(n_a), so this pass reads one field
     const double hl = 0.5 * A.f.lam;
     double acc = 0.0;
-    for (int q = threadIdx.x; q < N2; q += NT) {
-      const int at = real_at<L>(2 * q);
-      const double2 a = ni2[q], li = li2[q], b = na2[q];
-      acc += (-hl * li.x / sqrt(a.x) + hl * rl[at] / sqrt(b.x)) * (a.x - b.x);
-      acc += (-hl * li.y / sqrt(a.y) + hl * rl[at + 1] / sqrt(b.y)) * (a.y - b.y);
+    if (A.f.uvw_w) {
+      const double2* w2 = (const double2*)(A.f.uvw_w + off);
+      for (int q = threadIdx.x; q < N2; q += NT) {
+        const int at = real_at<L>(2 * q);
+        const double2 w = w2[q];
+        acc += hl * rl[at] * w.x;
+        acc += hl * rl[at + 1] * w.y;
+      }
+    } else {
+      const double2* ni2 = (const double2*)(A.f.n_i + off);
+      const double2* li2 = (const double2*)(A.f.lap_i + off);
+      const double2* na2 = (const double2*)(A.f.n_a + off);
+      for (int q = threadIdx.x; q < N2; q += NT) {
+        const int at = real_at<L>(2 * q);
+        const double2 a = ni2[q], li = li2[q], b = na2[q];
+        acc += (-hl * li.x / sqrt(a.x) + hl * rl[at] / sqrt(b.x)) * (a.x - b.x);
+        acc += (-hl * li.y / sqrt(a.y) + hl * rl[at + 1] / sqrt(b.y)) * (a.y - b.y);
+      }
     }
     acc = block_sum(acc, sh);
     if (threadIdx.x == 0) A.f.partials[bid] = acc;

@@ -170,6 +170,16 @@ __device__ inline void chunk_sums(const ActiveArgs& a, int64_t c, const double* 
         }
 #pragma unroll
         for (int g = 0; g < PG; ++g) acc[4] += ok[g] ? a.kT * sh_[g] * dn[g] : 0.0;  // kT (eta_i - eta_a) dn
+        if (a.uvw_w) {
+          // U_vW's v_vW[n_i] part, v_vW[n] = -(lambda/2) lap(sqrt n)/sqrt n, with U_xc;
+          // dn/sqrt(n_a) for the pass that sums the v_vW[n_a] part
+#pragma unroll
+          for (int g = 0; g < PG; ++g) {
+            const double li = a.lap_i[ip[g]];
+            acc[5] += ok[g] ? -0.5 * a.lam * li * rsqrt_nr(ni[g]) * dn[g] : 0.0;
+            if (ok[g]) a.uvw_w[ip[g]] = dn[g] * rsqrt_nr(na[g]);
+          }
+        }
       }
       if (printed) {
         // dn_a/dmu = (c_n / kT) dI_{1/2}/deta
@@ -961,6 +971,10 @@ void scf_build_iteration(arche_ctx* c) {
   const int nbv = fft_z_blocks(&c->plan);
   double* part_h = c->partials + scf_part_offset(c);
   double* part_v = part_h + nbh;
+  // With More and vW the SCF kernel sums U_vW's v_vW[n_i] part and leaves
+  // (n_i - n_a)/sqrt(n_a) in lap_a (free during the solve) for the C2R pass
+  // that sums the v_vW[n_a] part.
+  if (more && vw) c->active.uvw_w = c->lap_a;
   FftFuse f{};
   f.w = &c->state->w;
   f.n_i = c->n_i;
@@ -991,6 +1005,7 @@ void scf_build_iteration(arche_ctx* c) {
     push_dual(c->steps, SLOT_NHAT_A + 2, ps[2], pb[2]);
     FftFuse fv = f;
     fv.partials = part_v;
+    fv.uvw_w = c->lap_a;
     fft_c2r_passes(&c->plan, c->ctmp, c->ctmp, nullptr, 1.0 / g.vol, FUSE_NONE, C2R_OUT_UVW, fv, ps);
     if (!rt) push_pass(c->steps, SLOT_UVW, ps[0]);
     push_pass(c->steps, SLOT_UVW + 2, ps[2]);
@@ -1002,6 +1017,7 @@ void scf_build_iteration(arche_ctx* c) {
     push_fft(c->steps, SLOT_LAP_A, ps);
     FftFuse fv = f;
     fv.partials = part_v;
+    fv.uvw_w = c->lap_a;
     fft_c2r_passes(&c->plan, c->ctmp, c->ctmp, nullptr, 1.0 / g.vol, FUSE_NONE, C2R_OUT_UVW, fv, ps);
     push_fft(c->steps, SLOT_UVW, ps);
   }
