@@ -361,6 +361,25 @@ __global__ void __launch_bounds__(PLANE_NT) k_plane_dual(ZArgs A, ZArgs B, unsig
     plane_body<L, K2, M2>(B, blockIdx.x - n1, plane, tw, sh);
   }
 }
+// An x pass and a plane pass in one launch: the Hartree C2R's x pass (spectral
+// mixing on load) beside R2C(sqrt n_o)'s plane pass, both waiting only on the
+// mixing weight.  The x pass runs in tiles of TKX = N_h columns (one k_y row of
+// the (k_y, k_z) plane) with PLANE_NT threads, so that its N_y blocks take the
+// CUs the N_x plane blocks leave free, each block holding one tile in LDS.
+template <int L, int TKX, int SX, int MX, int K2, int M2>
+__global__ void __launch_bounds__(PLANE_NT) k_xplane_dual(StridedArgs A, ZArgs B, unsigned n1) {
+  constexpr int NE = plane_elems<L>() > strided_lds<L, TKX>() ? plane_elems<L>() : strided_lds<L, TKX>();
+  __shared__ cplx lds[NE];
+  __shared__ cplx tw[L];
+  __shared__ double sh[PLANE_NT / 64];
+  if (blockIdx.x < n1) {
+    if (fft_stopped(A.f)) return;
+    strided_body<L, TKX, SX, MX, PLANE_NT>(A, blockIdx.x, lds, tw, sh);
+  } else {
+    if (fft_stopped(B.f)) return;
+    plane_body<L, K2, M2>(B, blockIdx.x - n1, lds, tw, sh);
+  }
+}
 // The same for two strided passes of one line length and tile.
 template <int L, int TK, int S1, int M1, int S2, int M2, int NT>
 __global__ void __launch_bounds__(NT) k_strided_dual(StridedArgs A, StridedArgs B, unsigned n1) {
@@ -464,12 +483,24 @@ int plane_dir(const FftPass& p) {
 }
 
 // The pairs the SCF iteration launches together: R2C(n_a) with R2C(sqrt n_a)
-// (plane and x passes), and the Hartree C2R's plane pass with R2C(sqrt n_o)'s.
+// (plane and x passes); the Hartree C2R's x pass with R2C(sqrt n_o)'s plane
+// pass, and its plane pass with that of the C2R back from the Laplacian (or,
+// where the x length has no round trip, with R2C(sqrt n_o)'s plane pass).
 template <int L>
 bool launch_dual_L(const FftPass& a, const FftPass& b, hipStream_t s, hipError_t* e) {
   const dim3 blk_p(PLANE_NT);
   const int da = plane_dir(a), db = plane_dir(b);
-  if (da == 0 && a.mode == 0 && db == 0 && b.mode == 1) {
+  if (da == 1 && a.mode == 0 && db == 1 && b.mode == 0) {
+    hipLaunchKernelGGL((k_plane_dual<L, 1, 0, 1, 0>), dim3(a.nblocks + b.nblocks), blk_p, 0, s, a.z, b.z, a.nblocks);
+  } else if (a.kind == FFT_PASS_STRIDED && a.sign > 0 && a.mode == 3 && db == 0 && b.mode == 2) {
+    // the x pass re-tiled by N_h columns
+    constexpr int TKX = L / 2 + 1;
+    StridedArgs x = a.s;
+    const unsigned nouter = a.nblocks / (unsigned)a.s.nchunk;
+    x.nchunk = (x.ncols + TKX - 1) / TKX;
+    const unsigned n1 = nouter * (unsigned)x.nchunk;
+    hipLaunchKernelGGL((k_xplane_dual<L, TKX, +1, 3, 0, 2>), dim3(n1 + b.nblocks), blk_p, 0, s, x, b.z, n1);
+  } else if (da == 0 && a.mode == 0 && db == 0 && b.mode == 1) {
     hipLaunchKernelGGL((k_plane_dual<L, 0, 0, 0, 1>), dim3(a.nblocks + b.nblocks), blk_p, 0, s, a.z, b.z, a.nblocks);
   } else if (da == 1 && a.mode == 0 && db == 0 && b.mode == 2) {
     hipLaunchKernelGGL((k_plane_dual<L, 1, 0, 0, 2>), dim3(a.nblocks + b.nblocks), blk_p, 0, s, a.z, b.z, a.nblocks);

@@ -1032,12 +1032,20 @@ void scf_build_iteration(arche_ctx* c) {
     FftPass pe[3], pf[3];
     fft_c2r_passes(&c->plan, c->nhat_a, c->ctmp, c->VH, 1.0 / g.vol, C2R_IN_MIX, FUSE_NONE, f, pe);
     fft_r2c_passes(&c->plan, c->n_a, c->ctmp2, 1.0, g.dv, R2C_IN_MIX_SQRT, R2C_OUT_LAP, f, pf);
-    if (rt) pf[2].mode = 4;
+    fft_c2r_passes(&c->plan, c->ctmp2, c->ctmp2, c->lap_i, 1.0 / g.vol, FUSE_NONE, FUSE_NONE, f, ps);
+    if (rt) {
+      // the Hartree x pass beside R2C(sqrt n_o)'s plane pass; the Laplacian's
+      // round trip; the two C2R plane passes (-> V_H, -> lap sqrt(n_o)) together
+      pf[2].mode = 4;
+      push_dual(c->steps, SLOT_HARTREE, pe[0], pf[0]);
+      push_pass(c->steps, SLOT_SQRT_O + 2, pf[2]);
+      push_dual(c->steps, SLOT_HARTREE + 2, pe[2], ps[2]);
+      return;
+    }
     push_pass(c->steps, SLOT_HARTREE, pe[0]);
     push_dual(c->steps, SLOT_HARTREE + 2, pe[2], pf[0]);
     push_pass(c->steps, SLOT_SQRT_O + 2, pf[2]);
-    fft_c2r_passes(&c->plan, c->ctmp2, c->ctmp2, c->lap_i, 1.0 / g.vol, FUSE_NONE, FUSE_NONE, f, ps);
-    if (!rt) push_pass(c->steps, SLOT_LAP_O, ps[0]);
+    push_pass(c->steps, SLOT_LAP_O, ps[0]);
     push_pass(c->steps, SLOT_LAP_O + 2, ps[2]);
     return;
   }
