@@ -196,12 +196,13 @@ bool build_iteration_graph(arche_ctx* c) {
   return false;
 }
 
-// SCF loop.  Work is enqueued in units (a graph launch of ARCHE_GRAPH_ITERS
-// iterations, or single iterations for the tail below scf_max_iter and when
-// timing kernels), one unit ahead of the convergence poll: after enqueuing unit
-// u the host waits for unit u-1 and reads its iterations' states from the pinned
-// ring (the weight kernel of iteration t writes ring[(t-1) % ARCHE_RING]; two
-// units fit).  The state was reset by begin_solve; the iteration that meets the
+// SCF loop.  Work is enqueued in units of ARCHE_GRAPH_ITERS iterations (a graph
+// launch, or the iterations launch by launch when timing kernels; fewer for the
+// tail below scf_max_iter), one unit ahead of the convergence poll: after
+// enqueuing unit u the host waits for unit u-1 and reads its iterations' states
+// from the pinned ring (the weight kernel of iteration t writes
+// ring[(t-1) % ARCHE_RING]; two units fit).  Each unit boundary costs the device
+// a few microseconds, so units of several iterations also when timing.  The state was reset by begin_solve; the iteration that meets the
 // tolerance raises done and everything after it does nothing.  The polled states
 // are kept as the solve's convergence history.
 arche_status run_scf(arche_ctx* c, arche_result* out) {
@@ -239,13 +240,13 @@ arche_status run_scf(arche_ctx* c, arche_result* out) {
   };
   hipError_t e = hipSuccess;
   while (!stop && launched < max_iter && e == hipSuccess) {
-    if (graph && launched + ARCHE_GRAPH_ITERS <= max_iter) {
+    const int n = std::min(ARCHE_GRAPH_ITERS, max_iter - launched);
+    if (graph && n == ARCHE_GRAPH_ITERS) {
       e = hipGraphLaunch(c->iter_exec, c->stream);
-      launched += ARCHE_GRAPH_ITERS;
     } else {
-      e = scf_iteration(c);
-      launched += 1;
+      for (int i = 0; i < n && e == hipSuccess; ++i) e = scf_iteration(c);
     }
+    launched += n;
     if (e == hipSuccess) e = hipEventRecord(ev[unit & 1], c->stream);
     unit_end[unit & 1] = launched;
     if (e == hipSuccess && unit >= 1) {
