@@ -49,13 +49,15 @@ ITER_BYTES_PER_POINT = 216.0
 METRIC = "SCF iters/s + wall s per MD step (plain vs learned-init/batched), 1024 Al, 128³"
 
 
-def kernel_bytes(name, ng, nh, newton_per_launch):
+def kernel_bytes(name, ng, nh, newton_per_launch, more_frac=0.0):
     """Algorithmic HBM bytes of one launch of each timed kernel class."""
     if name == "scf_active":
         # potential assembly: read n_i, V^ie, V_H, lap sqrt(n_i) (32 B/pt); the Newton
         # passes read nothing (V_i and v_xc(n_i) stay in LDS); the last phase reads n_i and
-        # writes n_a (16 B/pt); V_i is written only by the iteration that ends the solve
-        return ng * 48.0
+        # writes n_a (16 B/pt); V_i is written only by the iteration that ends the solve.
+        # Once More's weight is on (a fraction more_frac of the launches) the last phase
+        # also reads lap sqrt(n_i) and writes (n_i - n_a)/sqrt(n_a) for the U_vW pass
+        return ng * (48.0 + 16.0 * more_frac)
     if name == "fft_z":
         # the z pass, or on N_y = N_z grids the fused z+y plane pass: real field in/out +
         # half spectrum out/in
@@ -427,13 +429,14 @@ def main():
     ev1 = torch.cuda.Event(enable_timing=True)
     ev0.record()
     t0 = time.perf_counter()
-    iters = newton = 0
+    iters = newton = more_iters = 0
     per_step, fallback, Ki, conserved = [], [], [], []
     for k in range(args.steps):
         pos, vel, F, res = ctx.md_step(dt, pos, vel)
         iters += res["scf_iters"]
         newton += res["newton_iters"]
         per_step.append(res["scf_iters"])
+        more_iters += int(np.sum(ctx.history()[:, 8] != 0))
         fallback.append(int(res["used_fallback"]))
         # the step returns v(t) (central difference) and F at t + dt: pair v(t) with
         # the previous step's free energy F(t) for the conserved K^i + F
@@ -456,12 +459,13 @@ def main():
     ctx.close()
 
     newton_per_launch = newton / max(iters, 1)
+    more_frac = more_iters / max(iters, 1)
 
     def table(pr, nl):
         out = {}
         for name, (ms, n) in pr.items():
             if n:
-                b = kernel_bytes(name, ng, nh, nl)
+                b = kernel_bytes(name, ng, nh, nl, more_frac)
                 out[name] = {"total_ms": ms, "launches": n, "avg_us": 1e3 * ms / n,
                              "alg_bytes_per_launch": b, "GBps": b / (ms / n * 1e-3) / 1e9}
         return out
@@ -480,6 +484,7 @@ def main():
     roofline = {"bound": "alu", "kernel": dom, "achieved": tflops, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": tflops / PEAK_FP64_TFLOPS, "traffic": traffic,
                 "alg_flops_per_launch": flops, "mu_evaluations_per_launch": newton_per_launch,
+                "more_weight_on_fraction": more_frac,
                 "counter_fp64_flops_per_launch": counter_flops_for(dom),
                 "alg_bytes_per_launch": d["alg_bytes_per_launch"], "hbm_GBps": d["GBps"],
                 "hbm_frac": d["GBps"] / PEAK_HBM_GBS, "avg_launch_us": d["avg_us"]}

@@ -937,6 +937,13 @@ hipError_t fft_tune(const FftPlan* p, cplx* scratch_c, double* scratch_r, hipStr
   for (int pass = 0; pass < 3 && e == hipSuccess; ++pass) {
     const int L = Ls[pass];
     if (L <= 96 || !ct_supported(L) || g_tuned[pass][L]) continue;
+    if (pass == 1 && fft_plane_fusable(p)) {
+      // on plane-pass grids the SCF iteration launches its x passes in pairs,
+      // which exist for the default tile only: keep it
+      g_tile_var[pass][L] = 0;
+      g_tuned[pass][L] = true;
+      continue;
+    }
     float best_ms = 0.f;
     int best = 0;
     for (int v = 0; v < 3 && e == hipSuccess; ++v) {
