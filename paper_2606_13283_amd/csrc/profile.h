@@ -26,8 +26,9 @@ struct Profiler {
 
   hipEvent_t take() {
     if (used == pool.size()) {
+      // timing only: no system-scope fence (its cache write-back would be timed)
       hipEvent_t e;
-      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
       pool.push_back(e);
     }
     return pool[used++];

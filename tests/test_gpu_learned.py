@@ -72,8 +72,6 @@ def test_learned_guess_saves_iterations(compared):
     assert lrn < plain
 
 
-@pytest.mark.xfail(strict=False, reason="trained on 80 samples, the network's proposal does not yet beat its own "
-                                        "input, the previous converged density (175 vs 156 iterations per step)")
 def test_learned_beats_previous_density(compared):
     """The network's gain over the method without it: fewer iterations than its
     own input, the previous converged density alone."""
