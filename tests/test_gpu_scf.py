@@ -279,6 +279,46 @@ def test_plane_grid_iteration_parity():
     assert any(abs(x - round(x / 0.05) * 0.05) > 1e-6 for x in r.weights[2:its - 1])
 
 
+def test_cubic_128_iteration_parity():
+    """Iteration-by-iteration parity on a 128^3 grid, the shape on which the
+    iteration also takes the Laplacian's x round trip (MODE 4: forward x pass,
+    multiply, inverse x pass on one tile), runs the Hartree C2R's x pass in one
+    launch with R2C(sqrt n_o)'s plane pass and pairs the two C2R plane passes
+    (-> V_H, -> lap sqrt(n_o)): 128 atoms, five iterations from the uniform
+    density with More's weight on from the third (trust bound lifted), against
+    the oracle's SCF loop (Sec. 2.5, 2.5.2): every residual and weight, and
+    element by element the last iteration's potential V_i (Sec. 2.2, built on
+    V_H and lap sqrt(n_i) from the previous iteration's passes) and active
+    density n_a."""
+    w = W.small_random(128, 128, 2.7, 10.0, seed=31)
+    say("128^3 iterations", w.name)
+    its = 5
+    ctx = arche.Context.from_workload(w, opts_of(w, init=arche.INIT_UNIFORM, scf_tol=1e-300, scf_max_iter=its,
+                                                 more_warmup=2, more_trust=1e30))
+    ctx.solve(w.pos, allow_noconv=True)
+    h = ctx.history()
+    Vi = ctx.debug("Vi")
+    na = ctx.debug("n_a")
+    ctx.close()
+    assert h.shape[0] == its
+    s = system_of(w)
+    ion = oscf.ionic_setup(s)
+    n0 = np.full(s.shape, s.Ne / s.grid.volume)
+    say("oracle iterations")
+    r = oscf.scf(s, ion, n0, mixing="more", tol=1e-300, max_iter=its, warmup=2, w_fixed=w.w_fixed, more_trust=1e30)
+    say("residuals gpu", h[:, 1], "oracle", r.history)
+    say("weights gpu", h[:, 2], "oracle", r.weights)
+    for t in range(its):
+        assert abs(h[t, 1] - r.history[t]) <= 1e-9 * r.history[t], (t, h[t, 1], r.history[t])
+    for t in range(its - 1):
+        assert abs(h[t, 2] - r.weights[t]) <= 1e-9, (t, h[t, 2], r.weights[t])
+    assert any(abs(x - round(x / 0.05) * 0.05) > 1e-6 for x in r.weights[2:its - 1])
+    dv = np.max(np.abs(Vi - r.V)) / np.max(np.abs(r.V))
+    dn = np.max(np.abs(na - r.n) / r.n)
+    say("max |V_i - V| / max |V|", dv, "max |n_a - n| / n", dn)
+    assert dv <= 1e-9 and dn <= 1e-9
+
+
 def test_plain_and_cooperative_launch_agree():
     """With exclusive_device set, the SCF kernel runs as a plain launch while its
     context is the only one alive and as a cooperative launch otherwise (the
