@@ -102,13 +102,25 @@ __device__ inline void vxc_group(const double* n, double* v) {
 //   between n_a and n_i, U_xc the same for v_xc; both only with with_k, else 0:
 //   the secant K inverts I_{1/2} at n_i, costly while n_i and n_a are far apart,
 //   and only More's weight uses it)
+// Two blocks share each CU, and a SIMD issues from the older block's waves
+// first when both are ready, so the younger one used to end a phase ~5 us after
+// the older one while the grid-wide reduction waited for it.  The first and the
+// second half of the grid (dispatched in that order, one block per CU each)
+// take turns at the higher wave priority from one group of points to the next,
+// so that both blocks of a CU finish a phase together.  Scheduling only: the
+// arithmetic and its order are unchanged.
+__device__ inline void take_turn(int group, bool young) {
+  if (((group & 1) != 0) == young) __builtin_amdgcn_s_setprio(1);
+  else __builtin_amdgcn_s_setprio(0);
+}
+
 // With CACHE, vls and xls (LDS, [PPT][SCF_THREADS]) hold the block's V_i and
 // v_xc(n_i) from the assembly.
 // FULL: every point of the chunk lies in the grid (N_g a multiple of SCF_CHUNK),
 // so the ragged-tail selects fold away.
 template <bool CACHE, bool ACTIVE, bool FULL = false>
 __device__ inline void chunk_sums(const ActiveArgs& a, int64_t c, const double* vls, const double* xls, double mu,
-                                  double ikT, const FdLds& fdl, double* sh, bool with_k = true) {
+                                  double ikT, const FdLds& fdl, double* sh, bool with_k = true, bool young = false) {
   const bool more = a.mixing == ARCHE_MIX_MORE && with_k;  // secant K and U_xc
   const bool printed = a.mixing == ARCHE_MIX_MORE_PRINTED;  // K = int dn^2 / (dn_a/dmu)
   const double icn = 1.0 / a.cn;
@@ -116,6 +128,7 @@ __device__ inline void chunk_sums(const ActiveArgs& a, int64_t c, const double* 
   double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll 1
   for (int q0 = 0; q0 < PPT; q0 += PG) {
+    take_turn(q0 / PG, young);
     int64_t ip[PG];
     bool ok[PG];
     double x[PG], ni[PG];
@@ -205,6 +218,7 @@ __device__ inline void chunk_sums(const ActiveArgs& a, int64_t c, const double* 
       }
     }
   }
+  __builtin_amdgcn_s_setprio(0);
   block_reduce_n<ACTIVE ? 8 : 2>(acc, ACTIVE ? 0x80u : 0u, sh);
   put_chunk_n<ACTIVE ? 8 : 2>(acc, a.part, 0, a.nchunk, c);
 }
@@ -252,6 +266,7 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
   const double ikT = 1.0 / kT;
   const double mu_prev = st->mu;  // NaN on the first iteration
   const bool try_prev = mu_prev == mu_prev;
+  const bool young = lb >= G / 2;  // the second half of the group (take_turn)
   // with CACHE each block owns at most one chunk (lb), otherwise chunks lb, lb+G, ...
 #define FOR_CHUNKS(c)                                           \
   for (int64_t c = lb; c < nchunk; c += (CACHE ? nchunk : G))
@@ -280,6 +295,7 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
     if (c != (int64_t)lb) fetch(c, 0);
 #pragma unroll 1
   for (int q0 = 0; q0 < PPT; q0 += PG) {
+      take_turn(q0 / PG, young);
       bool ok[PG];
       double n[PG], v[PG], lp[PG], vx[PG];
 #pragma unroll
@@ -324,6 +340,7 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
         }
       }
     }
+    __builtin_amdgcn_s_setprio(0);
     block_reduce_n<7>(acc, 0x6u, sh);
     put_chunk_n<7>(acc, a.part, 0, nchunk, c);
   }
@@ -385,10 +402,10 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
   while (!found && it < a.max_newton) {
     ++it;
     if (spec) {
-      FOR_CHUNKS(c) chunk_sums<CACHE, true, FULL>(a, c, vls, xls, mu, ikT, fdl, sh, k_on);
+      FOR_CHUNKS(c) chunk_sums<CACHE, true, FULL>(a, c, vls, xls, mu, ikT, fdl, sh, k_on, young);
       grid_allreduce(a.part, nchunk, a.res, 0, 8, 0x80u, G, lb, bank, ++nred, a.err, r, sh);
     } else {
-      FOR_CHUNKS(c) chunk_sums<CACHE, false, FULL>(a, c, vls, xls, mu, ikT, fdl, sh);
+      FOR_CHUNKS(c) chunk_sums<CACHE, false, FULL>(a, c, vls, xls, mu, ikT, fdl, sh, true, young);
       grid_allreduce(a.part, nchunk, a.res, 0, 2, 0u, G, lb, bank, ++nred, a.err, r, sh);
     }
     N = scale * r[0];
@@ -420,7 +437,7 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
 
   // 3. active density and the mixing reductions (unless the last pass formed them)
   if (!have_sums) {
-    FOR_CHUNKS(c) chunk_sums<CACHE, true, FULL>(a, c, vls, xls, mu, ikT, fdl, sh, k_on);
+    FOR_CHUNKS(c) chunk_sums<CACHE, true, FULL>(a, c, vls, xls, mu, ikT, fdl, sh, k_on, young);
     grid_allreduce(a.part, nchunk, a.res, 0, 8, 0x80u, G, lb, bank, ++nred, a.err, r, sh);
     for (int k = 0; k < 6; ++k) D[k] = r[2 + k];
   }
@@ -437,7 +454,7 @@ __device__ inline void scf_active_body(const ActiveArgs& a, unsigned lb, unsigne
       (MX <= a.trust || fabs(mu - mu_prev) <= MU_SETTLED * kT))
     more = 1;
   if (more && !k_on && a.mixing == ARCHE_MIX_MORE && !last) {
-    FOR_CHUNKS(c) chunk_sums<CACHE, true, FULL>(a, c, vls, xls, mu, ikT, fdl, sh, true);
+    FOR_CHUNKS(c) chunk_sums<CACHE, true, FULL>(a, c, vls, xls, mu, ikT, fdl, sh, true, young);
     grid_allreduce(a.part, nchunk, a.res, 0, 8, 0x80u, G, lb, bank, ++nred, a.err, r, sh);
     KK = r[4];
     UU = r[5];
