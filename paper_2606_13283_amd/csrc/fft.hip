@@ -290,14 +290,14 @@ constexpr int PLANE_NT = 1024;
 template <int L, int FIN>
 __global__ void __launch_bounds__(PLANE_NT) k_zy_r2c(ZArgs A) {
   if (fft_stopped(A.f)) return;
-  __shared__ cplx plane[plane_elems<L>()];
+  __shared__ cplx plane[plane_lds<L>()];
   __shared__ cplx tw[L];
   zy_r2c_body<L, FIN, PLANE_NT>(A, blockIdx.x, plane, tw);
 }
 template <int L, int FOUT>
 __global__ void __launch_bounds__(PLANE_NT) k_yz_c2r(ZArgs A) {
   if (fft_stopped(A.f)) return;
-  __shared__ cplx plane[plane_elems<L>()];
+  __shared__ cplx plane[plane_lds<L>()];
   __shared__ cplx tw[L];
   __shared__ double sh[PLANE_NT / 64];
   yz_c2r_body<L, FOUT, PLANE_NT>(A, blockIdx.x, plane, tw, sh);
@@ -350,7 +350,7 @@ __device__ inline void plane_body(const ZArgs& A, unsigned bid, cplx* plane, cpl
 }
 template <int L, int K1, int M1, int K2, int M2>
 __global__ void __launch_bounds__(PLANE_NT) k_plane_dual(ZArgs A, ZArgs B, unsigned n1) {
-  __shared__ cplx plane[plane_elems<L>()];
+  __shared__ cplx plane[plane_lds<L>()];
   __shared__ cplx tw[L];
   __shared__ double sh[PLANE_NT / 64];
   if (blockIdx.x < n1) {
@@ -368,7 +368,7 @@ __global__ void __launch_bounds__(PLANE_NT) k_plane_dual(ZArgs A, ZArgs B, unsig
 // CUs the N_x plane blocks leave free, each block holding one tile in LDS.
 template <int L, int TKX, int SX, int MX, int K2, int M2>
 __global__ void __launch_bounds__(PLANE_NT) k_xplane_dual(StridedArgs A, ZArgs B, unsigned n1) {
-  constexpr int NE = plane_elems<L>() > strided_lds<L, TKX>() ? plane_elems<L>() : strided_lds<L, TKX>();
+  constexpr int NE = plane_lds<L>() > strided_lds<L, TKX>() ? plane_lds<L>() : strided_lds<L, TKX>();
   __shared__ cplx lds[NE];
   __shared__ cplx tw[L];
   __shared__ double sh[PLANE_NT / 64];

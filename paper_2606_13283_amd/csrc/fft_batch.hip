@@ -20,7 +20,10 @@ constexpr int z_lds_need() {
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 constexpr int kMaxL = 96;
 constexpr int kStridedLds = cmax(cmax(strided_lds<96, CT_TK>(), strided_lds<80, CT_TK>()), strided_lds<72, CT_TK>());
-constexpr int kZLds = cmax(cmax(z_lds_need<96>(), z_lds_need<80>()), cmax(z_lds_need<72>(), z_lds_need<64>()));
+constexpr int kZLds = cmax(cmax(cmax(cmax(z_lds_need<96>(), z_lds_need<80>()), cmax(z_lds_need<72>(), z_lds_need<64>())),
+                                cmax(cmax(z_lds_need<60>(), z_lds_need<54>()), cmax(z_lds_need<50>(), z_lds_need<48>()))),
+                           cmax(cmax(cmax(z_lds_need<40>(), z_lds_need<32>()), cmax(z_lds_need<30>(), z_lds_need<24>())),
+                                cmax(z_lds_need<20>(), z_lds_need<16>())));
 
 __device__ inline int find_job(const int* __restrict__ bbeg, int njobs) {
   int lo = 0, hi = njobs - 1;

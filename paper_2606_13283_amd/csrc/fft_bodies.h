@@ -333,6 +333,11 @@ template <int L>
 constexpr int plane_elems() {
   return L * (L / 2 + 1);
 }
+// LDS of a plane pass: the plane, or its L/2 row pairs in the padded row layout
+template <int L>
+constexpr int plane_lds() {
+  return plane_elems<L>() > (L / 2) * row_pitch<L>() ? plane_elems<L>() : (L / 2) * row_pitch<L>();
+}
 
 struct PlaneOut {  // element (k_y = k, k_z = line) of the plane in global memory
   cplx* base;
@@ -384,8 +389,8 @@ template <int L, int FIN, int NT>
 __device__ inline void zy_r2c_body(const ZArgs& A, unsigned bid, cplx* plane, cplx* tw) {
   constexpr int Nh = L / 2 + 1;
   constexpr int NP = L / 2;
-  static_assert(NP * (L + 1) <= plane_elems<L>(), "packed rows fit the plane");
-  static_assert(NP * real_pair_pitch<L>() <= 2 * plane_elems<L>(), "real rows fit the plane");
+  static_assert(lds_size<L, NP, false>() <= plane_lds<L>(), "packed rows fit the plane's LDS");
+  static_assert(NP * real_pair_pitch<L>() <= 2 * plane_lds<L>(), "real rows fit the plane's LDS");
   static_assert(L % 2 == 0, "pairs of doubles");
   for (int i = threadIdx.x; i < L; i += NT) tw[i] = A.tw[i];
   const int64_t off = (int64_t)bid * L * L;

@@ -165,14 +165,31 @@ struct StageGeom {
 };
 
 // LDS element k of line `line`: line-interleaved layout for column tiles,
-// line-contiguous (with one complex of padding per line) for row tiles.
+// line-contiguous for row tiles.  A row tile's first stage writes each
+// butterfly's R0 outputs (R0 the plan's first radix) to consecutive elements,
+// so the lanes of one line store R0 elements apart, on the same LDS banks when
+// R0 >= 4: one complex of padding after every R0 elements spreads them over the
+// banks (and one more per line staggers neighbouring lines).
+template <int R, int... Rs>
+constexpr int first_radix(RList<R, Rs...>) {
+  return R;
+}
+template <int L>
+constexpr int row_pad() {
+  return first_radix(typename Plan<L>::R{}) >= 4 ? first_radix(typename Plan<L>::R{}) : 0;
+}
+template <int L>
+constexpr int row_pitch() {
+  return L + (row_pad<L>() ? L / row_pad<L>() : 0) + 1;
+}
 template <int L, int NL, bool LINE_FAST>
 __device__ inline int lds_at(int line, int k) {
-  return LINE_FAST ? k * NL + line : line * (L + 1) + k;
+  if constexpr (LINE_FAST) return k * NL + line;
+  else return line * row_pitch<L>() + k + (row_pad<L>() ? k / row_pad<L>() : 0);
 }
 template <int L, int NL, bool LINE_FAST>
 constexpr int lds_size() {
-  return LINE_FAST ? L * NL : NL * (L + 1);
+  return LINE_FAST ? L * NL : NL * row_pitch<L>();
 }
 
 // One Stockham stage: inputs from `In`, outputs to `Out`; twiddles from LDS table
