@@ -382,9 +382,23 @@ __device__ inline int real_at(int q) {
   return (y >> 1) * real_pair_pitch<L>() + (y & 1) * L + z;
 }
 
+// Element (k_z = line, y = k) of the half plane from the z transforms of the row
+// pairs (Z = X + i Y for rows 2l, 2l+1): X_k = (Z_k + conj Z_{L-k})/2,
+// Y_k = (Z_k - conj Z_{L-k})/(2i).
+template <int L>
+struct SplitIn {
+  LdsIO<L, L / 2, false> packed;
+  __device__ cplx operator()(int line, int k) const {
+    const cplx zk = packed(k >> 1, line);
+    const cplx zn = packed(k >> 1, line == 0 ? 0 : L - line);
+    return (k & 1) ? cplx{0.5 * (zk.y + zn.y), -0.5 * (zk.x - zn.x)} : cplx{0.5 * (zk.x + zn.x), 0.5 * (zk.y - zn.y)};
+  }
+};
+
 // R2C: the real plane is read once with coalesced 16-byte loads (input transform
 // FIN as in the z pass applied on the way) into LDS; z transform of its L/2 row
-// pairs, Hermitian split into the [k_y][k_z] plane, y transform, store.
+// pairs; y transform of the Hermitian split (formed as the first stage loads),
+// store.
 template <int L, int FIN, int NT>
 __device__ inline void zy_r2c_body(const ZArgs& A, unsigned bid, cplx* plane, cplx* tw) {
   constexpr int Nh = L / 2 + 1;
@@ -419,28 +433,10 @@ __device__ inline void zy_r2c_body(const ZArgs& A, unsigned bid, cplx* plane, cp
   __syncthreads();
   LdsIO<L, NP, false> packed{plane};
   run<L, NP, NT, false, -1, 1>(RealPairsIn<L>{rl}, packed, plane, tw, NP, typename Plan<L>::R{});
-  // split pair l into rows 2l, 2l+1 (read everything, then overwrite in place)
+  // the y transform reads the rows 2l, 2l+1 split out of pair l as it loads
+  // (its first stage has read everything before it overwrites the pairs)
   constexpr int NOUT = L * Nh;
-  constexpr int PER = (NOUT + NT - 1) / NT;
-  cplx v[PER];
-#pragma unroll
-  for (int p = 0; p < PER; ++p) {
-    const int q = threadIdx.x + NT * p;
-    if (q < NOUT) {
-      const int y = q / Nh, k = q - (q / Nh) * Nh;
-      const cplx zk = packed(y >> 1, k);
-      const cplx zn = packed(y >> 1, k == 0 ? 0 : L - k);
-      v[p] = (y & 1) ? cplx{0.5 * (zk.y + zn.y), -0.5 * (zk.x - zn.x)} : cplx{0.5 * (zk.x + zn.x), 0.5 * (zk.y - zn.y)};
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int p = 0; p < PER; ++p) {
-    const int q = threadIdx.x + NT * p;
-    if (q < NOUT) plane[q] = v[p];
-  }
-  __syncthreads();
-  run<L, Nh, NT, true, -1, 1>(LdsIO<L, Nh, true>{plane}, PlaneOut{(cplx*)A.out + (int64_t)bid * NOUT, Nh, A.out_scale},
+  run<L, Nh, NT, true, -1, 1>(SplitIn<L>{packed}, PlaneOut{(cplx*)A.out + (int64_t)bid * NOUT, Nh, A.out_scale},
                               plane, tw, Nh, typename Plan<L>::R{});
 }
 
