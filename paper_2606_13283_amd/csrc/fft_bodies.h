@@ -440,9 +440,9 @@ __device__ inline void zy_r2c_body(const ZArgs& A, unsigned bid, cplx* plane, cp
                               plane, tw, Nh, typename Plan<L>::R{});
 }
 
-// C2R: y transform of the plane into LDS, z transform of its row pairs into the
-// real plane in LDS, then one coalesced pass that stores it (or, FOUT = 1,
-// forms the U_vW partial sum of the z pass instead).
+// C2R: y transform of the plane into LDS, then the z transform of its row pairs,
+// whose last stage stores the real plane (FOUT = 0); for FOUT = 1 the real plane
+// goes to LDS and one coalesced pass forms the U_vW partial sum instead.
 template <int L, int FOUT, int NT>
 __device__ inline void yz_c2r_body(const ZArgs& A, unsigned bid, cplx* plane, cplx* tw, double* sh) {
   constexpr int Nh = L / 2 + 1;
@@ -452,18 +452,16 @@ __device__ inline void yz_c2r_body(const ZArgs& A, unsigned bid, cplx* plane, cp
   const cplx* in = (const cplx*)A.in + (int64_t)bid * L * Nh;
   LdsIO<L, Nh, true> pl{plane};
   run<L, Nh, NT, true, +1, 1>(ColIn{in, Nh, Nh}, pl, plane, tw, Nh, typename Plan<L>::R{});
-  double* rl = (double*)plane;
-  run<L, NP, NT, false, +1, 1>(HermIn{plane, L, Nh, NP}, RealPairsOut<L>{rl, A.out_scale}, plane, tw, NP,
-                               typename Plan<L>::R{});
   const int64_t off = (int64_t)bid * L * L;
-  constexpr int N2 = L * L / 2;
   if constexpr (FOUT == 0) {
-    double2* out2 = (double2*)((double*)A.out + off);
-    for (int q = threadIdx.x; q < N2; q += NT) {
-      const int at = real_at<L>(2 * q);
-      out2[q] = double2{rl[at], rl[at + 1]};
-    }
+    // the z transform's last stage stores the row pairs straight to the plane
+    run<L, NP, NT, false, +1, 1>(HermIn{plane, L, Nh, NP}, PairOut{(double*)A.out + off, L, NP, A.out_scale}, plane,
+                                 tw, NP, typename Plan<L>::R{});
   } else {
+    double* rl = (double*)plane;
+    run<L, NP, NT, false, +1, 1>(HermIn{plane, L, Nh, NP}, RealPairsOut<L>{rl, A.out_scale}, plane, tw, NP,
+                                 typename Plan<L>::R{});
+    constexpr int N2 = L * L / 2;
     // (v_vW[n_i] - v_vW[n_a]) (n_i - n_a) with v_vW[n] = -(lambda/2) lap / sqrt(n);
     // with uvw_w the SCF kernel has summed the v_vW[n_i] part and left
     // (n_i - n_a)/sqrt(n_a), so this pass reads one field
