@@ -369,8 +369,8 @@ def main():
                     help="only copy MIB MiB device to device 5 times (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs the whole path on a single MI355X "
-              "(multi-GPU sharding is a design note, not built); use --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library runs the whole path on a single MI355X "
+              "(sharding over several GPUs is described, not built); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
