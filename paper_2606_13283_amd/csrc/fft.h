@@ -176,6 +176,8 @@ bool fft_fusable(const FftPlan* p);
 bool fft_x_roundtrip(int L);
 // N_y = N_z with a plane kernel for that length (the plane fits in LDS)
 bool fft_plane_fusable(const FftPlan* p);
+// blocks of an x pass re-tiled by N_x/2 + 1 columns (its launch beside a plane pass)
+int fft_x_blocks_wide(const FftPlan* p);
 // number of blocks (= partial sums) of the fused x pass and of the fused z pass
 int fft_x_blocks(const FftPlan* p);
 int fft_z_blocks(const FftPlan* p);

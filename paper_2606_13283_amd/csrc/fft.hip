@@ -483,15 +483,24 @@ int plane_dir(const FftPass& p) {
 }
 
 // The pairs the SCF iteration launches together: R2C(n_a) with R2C(sqrt n_a)
-// (plane and x passes); the Hartree C2R's x pass with R2C(sqrt n_o)'s plane
-// pass, and its plane pass with that of the C2R back from the Laplacian (or,
-// where the x length has no round trip, with R2C(sqrt n_o)'s plane pass).
+// (plane and x passes, or where the x length has the round trip, the U_H x
+// pass with the U_vW plane pass); the Hartree C2R's x pass with R2C(sqrt n_o)'s
+// plane pass, and its plane pass with that of the C2R back from the Laplacian
+// (or, where the x length has no round trip, with R2C(sqrt n_o)'s plane pass).
 template <int L>
 bool launch_dual_L(const FftPass& a, const FftPass& b, hipStream_t s, hipError_t* e) {
   const dim3 blk_p(PLANE_NT);
   const int da = plane_dir(a), db = plane_dir(b);
   if (da == 1 && a.mode == 0 && db == 1 && b.mode == 0) {
     hipLaunchKernelGGL((k_plane_dual<L, 1, 0, 1, 0>), dim3(a.nblocks + b.nblocks), blk_p, 0, s, a.z, b.z, a.nblocks);
+  } else if (a.kind == FFT_PASS_STRIDED && a.sign < 0 && a.mode == 2 && db == 1 && b.mode == 1) {
+    // the U_H x pass re-tiled by N_h columns beside the U_vW plane pass
+    constexpr int TKX = L / 2 + 1;
+    StridedArgs x = a.s;
+    const unsigned nouter = a.nblocks / (unsigned)a.s.nchunk;
+    x.nchunk = (x.ncols + TKX - 1) / TKX;
+    const unsigned n1 = nouter * (unsigned)x.nchunk;
+    hipLaunchKernelGGL((k_xplane_dual<L, TKX, -1, 2, 1, 1>), dim3(n1 + b.nblocks), blk_p, 0, s, x, b.z, n1);
   } else if (a.kind == FFT_PASS_STRIDED && a.sign > 0 && a.mode == 3 && db == 0 && b.mode == 2) {
     // the x pass re-tiled by N_h columns
     constexpr int TKX = L / 2 + 1;
@@ -806,6 +815,10 @@ bool fft_fusable(const FftPlan* p) {
 }
 int fft_x_blocks(const FftPlan* p) {
   const int tk = kStridedTK[p->N[0] <= 1024 ? g_tile_var[1][p->N[0]] : 0];
+  return (p->N[1] * p->Nh + tk - 1) / tk;
+}
+int fft_x_blocks_wide(const FftPlan* p) {
+  const int tk = p->N[0] / 2 + 1;
   return (p->N[1] * p->Nh + tk - 1) / tk;
 }
 bool fft_x_roundtrip(int L) { return L == 128; }  // plane_len

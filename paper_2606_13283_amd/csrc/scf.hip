@@ -984,7 +984,16 @@ void scf_build_iteration(arche_ctx* c) {
   const arche_params& p = c->p;
   const bool vw = p.lambda_vw != 0.0;
   const bool more = p.mixing == ARCHE_MIX_MORE;
-  const int nbh = fft_x_blocks(&c->plan);
+  // With plane passes (N_y = N_z) independent transforms share launches (below).
+  const bool pair = fft_plane_fusable(&c->plan);
+  // Where the x length has it (rt), the Laplacian of sqrt n goes forward along
+  // x, is multiplied, and comes back along x at once (x pass MODE 4), so the C2R
+  // that follows starts at its plane pass.
+  const bool rt = pair && fft_x_roundtrip(g.N[0]);
+  // with More + vW on such grids the U_H x pass runs re-tiled beside the U_vW
+  // plane pass, in fewer blocks (fewer U_H partials)
+  const bool uh_wide = rt && more && vw;
+  const int nbh = uh_wide ? fft_x_blocks_wide(&c->plan) : fft_x_blocks(&c->plan);
   const int nbv = fft_z_blocks(&c->plan);
   double* part_h = c->partials + scf_part_offset(c);
   double* part_v = part_h + nbh;
@@ -1004,28 +1013,29 @@ void scf_build_iteration(arche_ctx* c) {
   f.L[2] = g.L[2];
   f.partials = part_h;
   f.stop = &c->state->done;
-  // With plane passes (N_y = N_z) independent transforms share launches: the
-  // plane and x passes of R2C(n_a) and R2C(sqrt n_a), and the Hartree C2R's plane
-  // pass with that of R2C(sqrt n_o), which then works in ctmp2.
-  const bool pair = fft_plane_fusable(&c->plan);
+  // Paired launches: the plane passes of R2C(n_a) and R2C(sqrt n_a); their x
+  // passes (or, with the round trip, the U_H x pass with the U_vW plane pass,
+  // the round trip alone before them); the Hartree C2R's plane pass with that
+  // of R2C(sqrt n_o), which then works in ctmp2.
   FftPass ps[3];
   fft_r2c_passes(&c->plan, c->n_a, c->nhat_a, 1.0, g.dv, FUSE_NONE, R2C_OUT_UH, f, ps);
-  // Where the x length has it (rt), the Laplacian of sqrt n goes forward along
-  // x, is multiplied, and comes back along x at once (x pass MODE 4), so the C2R
-  // that follows starts at its plane pass.
-  const bool rt = pair && fft_x_roundtrip(g.N[0]);
   if (pair && more && vw) {
-    FftPass pb[3];
+    FftPass pb[3], pu[3];
     fft_r2c_passes(&c->plan, c->n_a, c->ctmp, 1.0, g.dv, R2C_IN_SQRT, R2C_OUT_LAP, f, pb);
     if (rt) pb[2].mode = 4;
     push_dual(c->steps, SLOT_NHAT_A, ps[0], pb[0]);
-    push_dual(c->steps, SLOT_NHAT_A + 2, ps[2], pb[2]);
     FftFuse fv = f;
     fv.partials = part_v;
     fv.uvw_w = c->lap_a;
-    fft_c2r_passes(&c->plan, c->ctmp, c->ctmp, nullptr, 1.0 / g.vol, FUSE_NONE, C2R_OUT_UVW, fv, ps);
-    if (!rt) push_pass(c->steps, SLOT_UVW, ps[0]);
-    push_pass(c->steps, SLOT_UVW + 2, ps[2]);
+    fft_c2r_passes(&c->plan, c->ctmp, c->ctmp, nullptr, 1.0 / g.vol, FUSE_NONE, C2R_OUT_UVW, fv, pu);
+    if (rt) {
+      push_pass(c->steps, SLOT_LAP_A + 2, pb[2]);
+      push_dual(c->steps, SLOT_UVW + 2, ps[2], pu[2]);
+    } else {
+      push_dual(c->steps, SLOT_NHAT_A + 2, ps[2], pb[2]);
+      push_pass(c->steps, SLOT_UVW, pu[0]);
+      push_pass(c->steps, SLOT_UVW + 2, pu[2]);
+    }
   } else {
     push_fft(c->steps, SLOT_NHAT_A, ps);
   }
