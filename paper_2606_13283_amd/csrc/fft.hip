@@ -380,21 +380,6 @@ __global__ void __launch_bounds__(PLANE_NT) k_xplane_dual(StridedArgs A, ZArgs B
     plane_body<L, K2, M2>(B, blockIdx.x - n1, lds, tw, sh);
   }
 }
-// The same for two strided passes of one line length and tile.
-template <int L, int TK, int S1, int M1, int S2, int M2, int NT>
-__global__ void __launch_bounds__(NT) k_strided_dual(StridedArgs A, StridedArgs B, unsigned n1) {
-  __shared__ cplx lds[strided_lds<L, TK>()];
-  __shared__ cplx tw[L];
-  __shared__ double sh[NT / 64];
-  if (blockIdx.x < n1) {
-    if (fft_stopped(A.f)) return;
-    strided_body<L, TK, S1, M1, NT>(A, blockIdx.x, lds, tw, sh);
-  } else {
-    if (fft_stopped(B.f)) return;
-    strided_body<L, TK, S2, M2, NT>(B, blockIdx.x - n1, lds, tw, sh);
-  }
-}
-
 // Tile variants (autotuned per line length, fft.h): strided passes take TK
 // columns per block with NT threads, z passes B row pairs with NT threads.
 // Variant 0 is the default; line lengths of the batched set use only it.
@@ -482,11 +467,11 @@ int plane_dir(const FftPass& p) {
   return p.kind == FFT_PASS_ZY_R2C ? 0 : (p.kind == FFT_PASS_YZ_C2R ? 1 : -1);
 }
 
-// The pairs the SCF iteration launches together: R2C(n_a) with R2C(sqrt n_a)
-// (plane and x passes, or where the x length has the round trip, the U_H x
-// pass with the U_vW plane pass); the Hartree C2R's x pass with R2C(sqrt n_o)'s
-// plane pass, and its plane pass with that of the C2R back from the Laplacian
-// (or, where the x length has no round trip, with R2C(sqrt n_o)'s plane pass).
+// The pairs the SCF iteration launches together: the plane passes of R2C(n_a)
+// and R2C(sqrt n_a); where the x length has the round trip, the U_H x pass with
+// the U_vW plane pass, the Hartree C2R's x pass with R2C(sqrt n_o)'s plane pass,
+// and the Hartree C2R's plane pass with that of the C2R back from the
+// Laplacian (elsewhere, with R2C(sqrt n_o)'s plane pass).
 template <int L>
 bool launch_dual_L(const FftPass& a, const FftPass& b, hipStream_t s, hipError_t* e) {
   const dim3 blk_p(PLANE_NT);
@@ -513,14 +498,6 @@ bool launch_dual_L(const FftPass& a, const FftPass& b, hipStream_t s, hipError_t
     hipLaunchKernelGGL((k_plane_dual<L, 0, 0, 0, 1>), dim3(a.nblocks + b.nblocks), blk_p, 0, s, a.z, b.z, a.nblocks);
   } else if (da == 1 && a.mode == 0 && db == 0 && b.mode == 2) {
     hipLaunchKernelGGL((k_plane_dual<L, 1, 0, 0, 2>), dim3(a.nblocks + b.nblocks), blk_p, 0, s, a.z, b.z, a.nblocks);
-  } else if (a.kind == FFT_PASS_STRIDED && b.kind == FFT_PASS_STRIDED && a.var == 0 && b.var == 0 && a.sign < 0 &&
-             b.sign < 0 && a.mode == 2 && b.mode == 1) {
-    hipLaunchKernelGGL((k_strided_dual<L, kStridedTK[0], -1, 2, -1, 1, kStridedNT[0]>), dim3(a.nblocks + b.nblocks),
-                       dim3(kStridedNT[0]), 0, s, a.s, b.s, a.nblocks);
-  } else if (a.kind == FFT_PASS_STRIDED && b.kind == FFT_PASS_STRIDED && a.var == 0 && b.var == 0 && a.sign < 0 &&
-             a.mode == 2 && b.mode == 4) {
-    hipLaunchKernelGGL((k_strided_dual<L, kStridedTK[0], -1, 2, -1, 4, kStridedNT[0]>), dim3(a.nblocks + b.nblocks),
-                       dim3(kStridedNT[0]), 0, s, a.s, b.s, a.nblocks);
   } else {
     return false;
   }
@@ -951,8 +928,9 @@ hipError_t fft_tune(const FftPlan* p, cplx* scratch_c, double* scratch_r, hipStr
     const int L = Ls[pass];
     if (L <= 96 || !ct_supported(L) || g_tuned[pass][L]) continue;
     if (pass == 1 && fft_plane_fusable(p)) {
-      // on plane-pass grids the SCF iteration launches its x passes in pairs,
-      // which exist for the default tile only: keep it
+      // on plane-pass grids the SCF iteration's x passes run re-tiled beside
+      // plane passes or, the Laplacian round trips, alone, where the variants
+      // time within noise of each other: keep the default tile
       g_tile_var[pass][L] = 0;
       g_tuned[pass][L] = true;
       continue;

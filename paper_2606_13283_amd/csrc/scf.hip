@@ -1013,10 +1013,10 @@ void scf_build_iteration(arche_ctx* c) {
   f.L[2] = g.L[2];
   f.partials = part_h;
   f.stop = &c->state->done;
-  // Paired launches: the plane passes of R2C(n_a) and R2C(sqrt n_a); their x
-  // passes (or, with the round trip, the U_H x pass with the U_vW plane pass,
-  // the round trip alone before them); the Hartree C2R's plane pass with that
-  // of R2C(sqrt n_o), which then works in ctmp2.
+  // Paired launches: the plane passes of R2C(n_a) and R2C(sqrt n_a); with the
+  // round trip, the U_H x pass with the U_vW plane pass (the round trip alone
+  // before them; without it the x passes run one after the other); the Hartree
+  // C2R's plane pass with that of R2C(sqrt n_o), which then works in ctmp2.
   FftPass ps[3];
   fft_r2c_passes(&c->plan, c->n_a, c->nhat_a, 1.0, g.dv, FUSE_NONE, R2C_OUT_UH, f, ps);
   if (pair && more && vw) {
